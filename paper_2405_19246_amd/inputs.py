@@ -1,0 +1,101 @@
+"""Seeded synthetic marginals for entropic multi-marginal OT on a uniform 1-D grid.
+
+This module is shared by the tests, the benchmark and the oracle checks.  It only
+draws and normalises probability vectors; it holds none of the transport
+arithmetic (no kernel, no cost, no Sinkhorn step).
+
+Recipe (stands in for the paper's synthetic 1-D workloads of Sec. 5.1/5.2):
+  * grid x_i = i / (N - 1), i = 0..N-1, on [0, 1], step h = 1 / (N - 1)
+    (the paper puts N points uniformly on [0, 1], Sec. 5.1, and works on a
+    uniform mesh of step h, Sec. 3);
+  * each marginal is an equal-weight mixture of K Gaussians with means
+    U[0.2, 0.8] and standard deviations U[0.05, 0.15], evaluated at the nodes;
+  * then either a floor is added to the density before normalising
+    (``floor``), or the normalised mixture is blended with the uniform
+    distribution (``uniform_frac``);
+  * marginal q of instance s draws from numpy PCG64 seeded with the
+    sequence (master_seed, s, q), so every marginal is reproducible alone.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def grid_step(N: int) -> float:
+    """Grid step h of N uniform points on [0, 1]; a single point gets h = 1."""
+    return 1.0 / (N - 1) if N > 1 else 1.0
+
+
+def _rng(master_seed: int, instance: int, marginal: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([master_seed, instance, marginal])))
+
+
+def mixture_marginal(N: int, K: int, rng: np.random.Generator, floor: float = 1e-3,
+                     uniform_frac: float = 0.0) -> np.ndarray:
+    """One probability vector of length N (float64, sums to 1 up to rounding)."""
+    x = np.linspace(0.0, 1.0, N) if N > 1 else np.zeros(1)
+    mu = rng.uniform(0.2, 0.8, size=K)
+    sd = rng.uniform(0.05, 0.15, size=K)
+    dens = np.zeros(N)
+    for k in range(K):
+        dens += np.exp(-0.5 * ((x - mu[k]) / sd[k]) ** 2) / (sd[k] * np.sqrt(2.0 * np.pi))
+    dens /= K
+    if uniform_frac > 0.0:
+        p = dens / dens.sum()
+        p = (1.0 - uniform_frac) * p + uniform_frac / N
+    else:
+        p = dens + floor
+    return p / p.sum()
+
+
+def marginals(l: int, N: int, K: int = 2, master_seed: int = 0, instance: int = 0,
+              floor: float = 1e-3, uniform_frac: float = 0.0) -> np.ndarray:
+    """Array [l, N] of marginals for one instance."""
+    return np.stack([mixture_marginal(N, K, _rng(master_seed, instance, q), floor, uniform_frac)
+                     for q in range(l)])
+
+
+def uniform_random_marginals(l: int, N: int, seed: int = 0) -> np.ndarray:
+    """The paper's Sec. 5.1 recipe: i.i.d. U[0, 1] entries, each row normalised."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.uniform(0.0, 1.0, size=(l, N))
+    return u / u.sum(axis=1, keepdims=True)
+
+
+# Named workloads.  Each entry: l, N, K, eps, floor, uniform_frac.
+WORKLOADS = {
+    # plain method: l=3, N=64, 2 components, eps=0.1, fixed 500 sweeps
+    "l3_n64_eps0.1": dict(l=3, N=64, K=2, eps=0.1, floor=1e-3, uniform_frac=0.0),
+    # l=4, N=1000, 3 components, eps=1e-2
+    "l4_n1000_eps0.01": dict(l=4, N=1000, K=3, eps=1e-2, floor=1e-3, uniform_frac=0.0),
+    # dense comparator size of the same shape
+    "l4_n100_eps0.01": dict(l=4, N=100, K=3, eps=1e-2, floor=1e-3, uniform_frac=0.0),
+    # l=10, N=1e5, 5 components + 10% uniform, eps=1e-3
+    "l10_n100000_eps0.001": dict(l=10, N=100000, K=5, eps=1e-3, floor=0.0, uniform_frac=0.1),
+}
+
+
+def workload(name: str, instance: int = 0, master_seed: int = 0):
+    """(u [l, N], h, eps) for a named workload and instance index."""
+    w = WORKLOADS[name]
+    u = marginals(w["l"], w["N"], w["K"], master_seed, instance, w["floor"], w["uniform_frac"])
+    return u, grid_step(w["N"]), w["eps"]
+
+
+def batch_instances(count: int, master_seed: int = 0, l_range=(3, 8), n_range=(256, 65536),
+                    eps_choices=(1e-1, 1e-2, 1e-3), K: int = 3):
+    """Uneven batch: l uniform in l_range, N log-uniform in n_range, eps from eps_choices.
+
+    Returns a list of dicts {l, N, h, eps, u}.  The shape draw uses its own
+    stream (master_seed, -1) so that instance s's marginals do not depend on
+    how many instances are drawn.
+    """
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([master_seed, 2**31 - 1])))
+    out = []
+    for s in range(count):
+        l = int(rng.integers(l_range[0], l_range[1] + 1))
+        N = int(round(float(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))))
+        eps = float(eps_choices[int(rng.integers(0, len(eps_choices)))])
+        u = marginals(l, N, K, master_seed, s)
+        out.append(dict(l=l, N=N, h=grid_step(N), eps=eps, u=u))
+    return out
