@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark: l*N*Sinkhorn-iterations per second at fixed marginal error, 1 MI355X.
+
+Workload (one "step"): a batch of seeded synthetic instances of the l = 4,
+N = 1000, eps = 1e-2 problem (3-component Gaussian-mixture marginals on a
+uniform grid of [0, 1], +1e-3 floor, normalised), each solved to the FP64
+marginal error Res <= 1e-6 with FP32 scans, FP64 checks every 10 sweeps and an
+FP64 objective -- all of it in ONE persistent launch (mmot_solve_batch).
+Inputs are resident in device memory before the timed region.
+
+value = sum over instances of l * N * sweeps, divided by the wall time of the
+K timed steps (bracketed by device synchronisation).
+
+Extra fields: the same batch in FP64 to Res <= 1e-8; the plain
+one-solve-per-launch form at the same accuracy and the batched speed-up; a
+short continuous-batching serving run with p50/p99 latency; the roofline of
+the batch kernel; and the oracle timed on host cores on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--instances B]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "l4_n1000_eps0.01"
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_source_sha1() -> str:
+    d = os.path.join(ROOT, "paper_2405_19246_amd", "csrc")
+    h = hashlib.sha1()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hpp", ".hip", ".cpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def make_batch(count: int, dev):
+    import torch
+    from paper_2405_19246_amd import inputs
+    insts = []
+    for s in range(count):
+        u, h, eps = inputs.workload(WORKLOAD, instance=s)
+        l, N = u.shape
+        insts.append(dict(l=l, N=N, h=h, eps=eps, u=u,
+                          log_u=torch.tensor(np.log(u), dtype=torch.float64, device=dev),
+                          log_phi=torch.zeros((l, N), dtype=torch.float64, device=dev)))
+    return insts
+
+
+def timed(fn):
+    import torch
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    out = fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return out, e0.elapsed_time(e1) / 1e3
+
+
+def units_of(res):
+    return float(sum(r["l"] * r["N"] * r["iters"] for r in res))
+
+
+def traffic_entry(sha: str):
+    path = os.path.join(ROOT, "profiles", "traffic_k_solve_batch_l4_n1000.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except Exception:
+        return None
+    if t.get("kernel_src_sha1") != sha:
+        return None
+    return t
+
+
+def cpu_baseline(seconds: float):
+    """The oracle (FP64 C checker, one thread) on instances of the same workload."""
+    from oracle import fastcheck
+    from paper_2405_19246_amd import inputs
+    t0 = time.perf_counter()
+    units = 0.0
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        u, h, eps = inputs.workload(WORKLOAD, instance=n)
+        r = fastcheck.sinkhorn(u, h, eps, itmax=20000, tol=1e-6, check_every=10)
+        units += u.shape[0] * u.shape[1] * r["iters"]
+        n += 1
+    dt = time.perf_counter() - t0
+    return dict(value=units / dt, unit="l*N*sweeps/s", cores=1, kind="oracle",
+                sample="%d instances of %s solved to Res<=1e-6 by oracle/fastcheck.c (FP64, 1 thread), %.1f s"
+                       % (n, WORKLOAD, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--instances", type=int, default=1024)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: instances are independent and would shard across GPUs "
+              "with no communication; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2405_19246_amd import mmot
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    mmot.lib()
+    tol32, tol64 = 1e-6, 1e-8
+    batch = make_batch(args.instances, dev)
+
+    def step(prec, tol):
+        return mmot.solve_batch(batch, precision=prec, tol=tol, itr_max=20000, check_every=10)
+
+    for _ in range(args.warmup):
+        step(mmot.FP32, tol32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    units = 0.0
+    kern_ms = []
+    res = None
+    for _ in range(args.steps):
+        res = step(mmot.FP32, tol32)
+        units += units_of(res)
+        kern_ms.append(mmot.last_batch_kernel_ms())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = units / wall
+    ok = all(r["status"] == 0 and r["marg_err"] <= tol32 for r in res)
+    iters = np.array([r["iters"] for r in res])
+
+    per_launch_units = units / args.steps
+    k_ms = float(np.mean(kern_ms))
+    bytes_per_unit = (4 + 1) * 8  # read l-1 potential rows and log u_j, write a_j: (l + 1) FP64 per update
+    achieved = per_launch_units * bytes_per_unit / (k_ms / 1e3) / 1e9
+    sha = kernel_source_sha1()
+    tr = traffic_entry(sha)
+    roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
+                    traffic=(tr["hbm_bytes_per_launch"] if tr else None),
+                    kernel="k_solve_batch<float>", kernel_ms=k_ms, bytes_per_unit=bytes_per_unit,
+                    units_per_launch=per_launch_units)
+
+    out = {
+        "metric": "l*N*Sinkhorn-iters/sec at fixed marginal error (Res<=1e-6, FP64-checked)",
+        "value": value,
+        "unit": "marginal-position updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussian-mixture marginals)",
+        "config": {"workload": "%s: batch of %d instances, l=4, N=1000, eps=1e-2, FP32 scans to Res<=1e-6"
+                               % (WORKLOAD, args.instances),
+                   "l": 4, "N": 1000, "eps": 0.01, "instances": args.instances, "tol": tol32,
+                   "check_every": 10, "parallelism": "one wavefront per instance, persistent launch"},
+        "all_converged": ok,
+        "sweeps": {"min": int(iters.min()), "median": float(np.median(iters)), "max": int(iters.max())},
+        "roofline": roofline,
+    }
+
+    if not args.no_extras:
+        # FP64 scans to Res <= 1e-8
+        (r64, t64) = timed(lambda: step(mmot.FP64, tol64))
+        out["fp64"] = dict(value=units_of(r64) / t64, tol=tol64, seconds=t64,
+                           all_converged=all(r["status"] == 0 for r in r64),
+                           kernel_ms=mmot.last_batch_kernel_ms())
+        # plain form: one solve per launch, same accuracy, a subset of the batch
+        nplain = min(16, args.instances)
+        plans = [mmot.Plan(4, 1000, batch[i]["h"], batch[i]["eps"], precision=mmot.FP32, tol=tol32,
+                           itr_max=20000, check_every=10) for i in range(nplain)]
+
+        def plain():
+            return [plans[i].solve(batch[i]["log_u"], batch[i]["log_phi"])[1] for i in range(nplain)]
+
+        plain()
+        (rp, tp) = timed(plain)
+        plain_rate = units_of(rp) / tp
+        out["plain_one_solve_per_launch"] = dict(value=plain_rate, instances=nplain, seconds=tp,
+                                                 batched_speedup=value / plain_rate)
+        # continuous-batching serving: Poisson arrivals of the same problem shape
+        from paper_2405_19246_amd import inputs
+        rate, dur = 2000.0, 2.0
+        rng = np.random.default_rng(0)
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * dur * 1.2)))
+        arr = arr[arr < dur]
+        us = [inputs.workload(WORKLOAD, instance=10000 + i)[0] for i in range(64)]
+        h0, e0 = inputs.grid_step(1000), 0.01
+
+        def gen(i):
+            if i >= len(arr):
+                return None
+            return us[i % len(us)], h0, e0, float(arr[i])
+
+        st = mmot.serve(gen, precision=mmot.FP32, tol=tol32, itr_max=20000, check_every=10, max_slots=2048,
+                        block_sweeps=100, hbm_budget_bytes=16 << 30)
+        out["serve"] = dict(offered_req_per_s=rate, seconds_of_arrivals=dur, requests=int(len(arr)),
+                            completed=st["completed"], p50_latency_s=st["p50_latency"],
+                            p99_latency_s=st["p99_latency"], units_per_second=st["units_per_second"],
+                            wall_seconds=st["wall_seconds"], workload=WORKLOAD + " requests")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    out["kernel_src_sha1"] = sha
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

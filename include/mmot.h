@@ -1,0 +1,245 @@
+/*
+ * mmot.h -- C ABI of libmmot, entropic multi-marginal optimal transport with
+ * L1 cost on a uniform 1-D grid, solved by Gauss-Seidel Sinkhorn whose
+ * tensor-vector products run in O(N) per marginal on an MI355X (gfx950).
+ *
+ * Problem (Sec. 2 and Sec. 4.2 of arXiv:2405.19246).  l probability vectors
+ * u_1..u_l of common length N live on a uniform grid of step h.  The cost of an
+ * index tuple is c(i_1..i_l) = h * sum_{p<q} |i_p - i_q|, the Gibbs kernel is
+ * K = exp(-c / eps) = lambda^{sum |i_p - i_q|} with lambda = exp(-h / eps), and
+ * the entropic plan has the Gibbs form t = K * prod_q phi_q(i_q).  Sinkhorn
+ * updates phi_j <- u_j / (K x_{q != j} phi_q) for j = 1..l in order, each
+ * product using the newest phi's (Gauss-Seidel, Sec. 4.2 update formulas).
+ *
+ * Conventions shared by every entry point:
+ *  - Scaling vectors are passed as log-potentials a_q = log phi_q (natural
+ *    log, FP64), row-major [l][N]; marginals as log u_q, FP64 [l][N].  A zero
+ *    marginal entry is log u = -inf and gives a = -inf (phi = 0).
+ *  - "device" pointers are HIP device memory on the current device (e.g. the
+ *    data pointer of a torch CUDA tensor); "host" pointers are CPU memory.
+ *    The caller owns every buffer it passes; the library never frees them.
+ *  - Work is enqueued on the plan's HIP stream (NULL = default stream).
+ *    Entry points that return host values synchronise that stream first.
+ *  - Return value: MMOT_OK (0) or a negative MMOT_ERR_* code; the message of
+ *    the last error on the calling thread is mmot_last_error().  No C++
+ *    exception crosses this interface.
+ *  - precision MMOT_FP64: every scan runs in FP64 mantissas.  MMOT_FP32: the
+ *    scans of the Sinkhorn updates run in FP32 mantissas with exact integer
+ *    power-of-two exponents per value; potentials, the marginal-error check and
+ *    the objective stay FP64.
+ */
+#ifndef MMOT_H
+#define MMOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MMOT_OK 0
+#define MMOT_ERR_INVALID (-1)     /* bad argument: l < 2, l > MMOT_MAX_L, N < 1, eps <= 0, h <= 0, j out of range, NULL */
+#define MMOT_ERR_NOMEM (-2)       /* device or host allocation failed */
+#define MMOT_ERR_NUMERIC (-3)     /* a NaN or infinity appeared in a potential, the residual or the objective */
+#define MMOT_NOT_CONVERGED (-4)   /* itr_max reached with residual > tol; outputs are still written */
+#define MMOT_ERR_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define MMOT_ERR_HIP (-6)         /* a HIP runtime call failed (message names it) */
+#define MMOT_ERR_STATE (-7)       /* server stopped, unknown ticket, or call out of order */
+
+#define MMOT_MAX_L 8              /* largest number of marginals per problem */
+
+#define MMOT_FP64 0
+#define MMOT_FP32 1
+
+/* One problem shape: l marginals of length N on a grid of step h, entropic eps. */
+typedef struct {
+    int32_t l;
+    int64_t N;
+    double h;
+    double eps;
+    int32_t precision; /* MMOT_FP64 or MMOT_FP32 */
+} mmot_problem;
+
+/* Stopping rule of Alg. 1: stop after itr_max sweeps or once Res <= tol, where
+ * Res = sum_{j < l} || phi_j * (K x_{q != j} phi_q) - u_j ||_1 (the last marginal
+ * is exact after its own update) is evaluated in FP64 after every check_every-th
+ * sweep.  tol < 0 never stops early.  flags: MMOT_FLAG_WARM_START keeps the
+ * potentials passed in instead of starting from phi = 1/N (Alg. 1 init). */
+typedef struct {
+    double tol;
+    int64_t itr_max;
+    int32_t check_every;
+    int32_t flags;
+} mmot_opts;
+
+#define MMOT_FLAG_WARM_START 1
+
+/* Per-solve outcome. */
+typedef struct {
+    double W;          /* W_eps = <C, T>, transport cost of the plan (Sec. 2 Eq. mmot distance), FP64 */
+    double marg_err;   /* last Res (FP64), see mmot_opts */
+    int64_t iters;     /* sweeps done */
+    int32_t status;    /* MMOT_OK, MMOT_NOT_CONVERGED or MMOT_ERR_NUMERIC */
+    int32_t l;
+    int64_t N;
+} mmot_result;
+
+typedef struct mmot_plan mmot_plan_t;
+
+/*
+ * Build an execution plan for one problem shape: validates the problem,
+ * derives lambda = exp(-h/eps) and the discount tables of the scans, picks the
+ * launch shape and allocates the device workspace (constants, scan
+ * checkpoints, result slot).  This is not the transport plan.
+ * hip_stream: a hipStream_t or NULL.  *out receives the plan (caller destroys it).
+ */
+int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_plan_t **out);
+
+/* Device bytes the plan holds, plus the caller buffers one solve needs
+ * (2 * l * N doubles), for admission by HBM footprint. */
+int mmot_plan_footprint(const mmot_plan_t *plan, size_t *device_bytes);
+
+int mmot_plan_destroy(mmot_plan_t *plan);
+
+/*
+ * One tensor-vector product (Sec. 4.2 Eq. for J^{(l)}; Sec. 3.1 FTVP-1 for l = 3):
+ *   log_J[y] = log sum_{i_q, q != j; i_j = y} K(i) prod_{q != j} phi_q(i_q).
+ * j: 0-based marginal index.  log_phi: device [l][N] FP64, row j ignored.
+ * log_J: device [N] FP64, written.  Runs in the plan's precision.
+ */
+int mmot_marginal_product(const mmot_plan_t *plan, int32_t j, const double *log_phi, double *log_J);
+
+/*
+ * n_sweeps Gauss-Seidel sweeps (Alg. 1 loop body, l updates each) starting
+ * from the potentials in log_phi, no early stop; warm start = resume.
+ * log_u: device [l][N].  log_phi: device [l][N], in/out.
+ * marg_err: host, nullable; if given, Res after the last sweep is computed in
+ * FP64 and the stream is synchronised.
+ */
+int mmot_sinkhorn_iter(const mmot_plan_t *plan, const double *log_u, double *log_phi, int64_t n_sweeps,
+                       double *marg_err);
+
+/*
+ * Whole solve in one launch (Alg. 1 / Alg. FS-3): start from phi = 1/N unless
+ * MMOT_FLAG_WARM_START, iterate until Res <= tol or itr_max, then compute W_eps
+ * in FP64.  log_u: device [l][N].  log_phi: device [l][N] out (in/out with
+ * warm start).  res: host, written after the stream is synchronised.  Returns
+ * MMOT_OK, MMOT_NOT_CONVERGED or an error; res->status carries the same.
+ */
+int mmot_solve(const mmot_plan_t *plan, const double *log_u, double *log_phi, mmot_result *res);
+
+/* W_eps = <C, T> of the plan with potentials log_phi (Sec. 2 Eq. mmot distance;
+ * Sec. 3.2 FTVP-2 for l = 3), FP64.  W: host, synchronises. */
+int mmot_objective(const mmot_plan_t *plan, const double *log_phi, double *W);
+
+/* FP64 L1 errors of all l marginals of the plan with potentials log_phi:
+ * err[j] = || phi_j * (K x_{q != j} phi_q) - u_j ||_1.  err: host [l], synchronises. */
+int mmot_marginal_errors(const mmot_plan_t *plan, const double *log_u, const double *log_phi, double *err);
+
+/* One instance of a batch or serving request.  log_u / log_phi: device [l][N]. */
+typedef struct {
+    int32_t l;
+    int64_t N;
+    double h;
+    double eps;
+    const double *log_u;
+    double *log_phi;
+} mmot_instance;
+
+/*
+ * Solve `count` independent instances of mixed l, N, eps in ONE persistent
+ * launch: each wavefront takes the next unsolved instance (largest estimated
+ * work first) until none is left, and runs its whole solve (sweeps, FP64
+ * checks every o->check_every sweeps, FP64 objective).  precision as in
+ * mmot_problem.  res: host [count], written after synchronising hip_stream.
+ * Returns MMOT_OK if every instance converged, MMOT_NOT_CONVERGED if some hit
+ * itr_max, MMOT_ERR_NUMERIC if some failed; per-instance status is in res.
+ */
+int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_t precision, const mmot_opts *o,
+                     void *hip_stream, mmot_result *res);
+
+/* Device time in milliseconds of the last persistent batch launch (the kernel
+ * alone, between two HIP events recorded on its stream around the launch; the
+ * ticket reset and descriptor copies are outside).  Covers mmot_solve_batch and
+ * the server's rounds.  *ms: host.  MMOT_ERR_STATE before the first launch. */
+int mmot_last_batch_kernel_ms(double *ms);
+
+/* ---------------- serving (continuous batching) ---------------- */
+
+typedef struct mmot_server mmot_server_t;
+
+typedef struct {
+    int32_t precision;        /* MMOT_FP64 / MMOT_FP32 */
+    mmot_opts opts;           /* per-request stopping rule */
+    int32_t max_slots;        /* instances resident on the device at once */
+    int64_t block_sweeps;     /* sweeps each resident solve advances per device round */
+    size_t hbm_budget_bytes;  /* admission limit on the summed device footprint */
+} mmot_serve_cfg;
+
+/* A request: marginals are host memory, copied at admission. */
+typedef struct {
+    int32_t l;
+    int64_t N;
+    double h;
+    double eps;
+    const double *u;          /* host [l][N], probability vectors */
+} mmot_request;
+
+/* Per-request record.  Times are seconds on the server's monotonic clock. */
+typedef struct {
+    mmot_result result;
+    double t_submit;
+    double t_admit;
+    double t_done;
+} mmot_request_record;
+
+/*
+ * Start a server thread that owns a HIP stream and a device arena.  Requests
+ * submitted while others are running are admitted into free slots at the next
+ * device-round boundary when their footprint fits the HBM budget; resident
+ * solves keep their potentials on the device across rounds.
+ */
+int mmot_serve_start(const mmot_serve_cfg *cfg, mmot_server_t **out);
+
+/* Queue a request (marginals copied before return).  *ticket identifies it. */
+int mmot_serve_submit(mmot_server_t *srv, const mmot_request *req, uint64_t *ticket);
+
+/* Non-blocking: 1 and *rec filled if the request finished, 0 if not yet, <0 error.
+ * log_phi_out: host [l][N] or NULL, receives the final potentials. */
+int mmot_serve_poll(mmot_server_t *srv, uint64_t ticket, mmot_request_record *rec, double *log_phi_out);
+
+/* Finish queued and running work, stop the thread, free the device arena. */
+int mmot_serve_stop(mmot_server_t *srv);
+
+/* Summary of a blocking serving run. */
+typedef struct {
+    int64_t completed;
+    int64_t rejected;          /* footprint above the whole budget */
+    double wall_seconds;
+    double p50_latency;        /* seconds, submit to done */
+    double p99_latency;
+    double units_per_second;   /* sum over requests of l * N * iters / wall time */
+} mmot_serve_stats;
+
+/* Callback for the blocking server: fill *req and *t_arrive (seconds from the
+ * start) for request number `index`; return 0 to submit it, 1 when there are no
+ * more requests.  The request's u must stay valid until the call returns. */
+typedef int (*mmot_request_fn)(void *user, int64_t index, mmot_request *req, double *t_arrive);
+
+/*
+ * Blocking serving loop: submits each request at its arrival time (open loop),
+ * runs until all are done, fills *stats; records: host array of at least the
+ * number of requests, or NULL.
+ */
+int mmot_serve(const mmot_serve_cfg *cfg, mmot_request_fn next, void *user, mmot_serve_stats *stats,
+               mmot_request_record *records, int64_t max_records);
+
+/* Message of the last error on this thread (empty string if none). */
+const char *mmot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMOT_H */

@@ -1,0 +1,112 @@
+// Definitions shared by the host runtime and the device kernels of libmmot.
+#pragma once
+#include <stdint.h>
+
+namespace mmot {
+
+constexpr int MAXL = 8;   // largest number of marginals (MMOT_MAX_L)
+constexpr int MAXV = 8;   // largest number of grid positions one lane owns per chunk
+constexpr int WAVE = 64;  // CDNA wavefront width
+
+// Exponent that marks zero.  Far below any real value's exponent and far from
+// int32 overflow when a few are added.
+constexpr int32_t XF_ZERO_E = -(1 << 26);
+
+// Extended-range floating point: value = m * 2^e with m a float or double
+// mantissa (normalised to [0.5, 1) after additions, 0 for zero) and an exact
+// int32 power-of-two exponent.  It plays the role of a log-sum-exp shift that
+// is exact: no value of the transport problem over- or underflows, whatever
+// the size of the potentials, and adding two values costs one alignment.
+template <typename M>
+struct XF {
+    M m;
+    int32_t e;
+};
+
+// A discount factor g^p as an extended-range value whose mantissa is carried
+// to twice the working precision (hi + lo): the factors are applied again and
+// again along a scan, so a mantissa rounded once would bias every result.
+template <typename M>
+struct XG {
+    M hi;
+    M lo;
+    int32_t e;
+    int32_t pad;
+};
+
+// Discount constants of one instance for scans of width V, mantissa M.
+// g(k) = lambda^{k (l - k)} is the factor a state with k of the l - 1 summed
+// marginals already placed picks up per grid gap (gap form of the L1 cost).
+template <typename M>
+struct Disc {
+    XG<M> g1[MAXL];           // g(k)
+    XG<M> gstep[MAXL][6];     // g(k)^(V * 2^s), Kogge-Stone steps across lanes
+    XG<M> gfix[MAXL][MAXV];   // g(k)^(t + 1), carry fix-up inside a lane
+    double lgV[MAXL];         // V * ln g(k), for the per-lane power g(k)^(V * lane)
+    double ck[MAXL + 1];      // k (l - k), gap count weight for the objective
+    int32_t V;
+    int32_t pad;
+};
+
+// Shape and discount constants of one problem (written once, read-only).
+struct Inst {
+    int64_t N;
+    int32_t l;
+    int32_t pad;
+    double h;
+    double hoe;           // h / eps
+    Disc<float> d32;      // FP32 update scans
+    Disc<double> d64;     // FP64 update and check scans
+    Disc<double> dob;     // FP64 objective scans (value, cost-weighted value)
+    Disc<double> dck;     // FP64 residual-check scans
+};
+
+// Buffers of one solve (caller-owned except scratch).
+struct Ptrs {
+    const double *log_u;  // [l][N] log marginals
+    double *a;            // [l][N] log potentials (in/out)
+    double *out;          // [N] product output (log J), product mode only
+    void *scratch;        // per-chunk scan checkpoints
+    int64_t itr_cap;      // sweeps allowed for this instance in this launch (0: RunOpts.itr_max)
+    int32_t flags;        // OR-ed with RunOpts.flags
+    int32_t pad;
+};
+
+// Stopping rule of one launch.
+struct RunOpts {
+    double tol;           // stop once Res <= tol (tol < 0: never early)
+    int64_t itr_max;      // sweeps in this launch
+    int32_t check_every;  // Res every this many sweeps (0: only after the last)
+    int32_t flags;
+};
+
+// Same layout as mmot_result.
+struct Result {
+    double W;
+    double marg_err;
+    int64_t iters;
+    int32_t status;
+    int32_t l;
+    int64_t N;
+};
+
+// Inst.flags
+constexpr int32_t F_WARM = 1;        // keep the given potentials
+constexpr int32_t F_NO_CHECK = 2;    // no residual check at all
+constexpr int32_t F_NO_OBJ = 4;      // skip the objective
+
+// Lane width V per (l, pass kind) -- trades registers against scan overhead.
+// kind 0: FP32 update, 1: FP64 update and product, 2: FP64 objective
+// (value, weighted value), 3: FP64 residual check.
+constexpr int vsel(int l, int kind)
+{
+    return kind == 0 ? (l <= 3 ? 8 : l == 4 ? 4 : l == 5 ? 2 : 1)
+         : kind == 1 ? (l <= 2 ? 8 : l == 3 ? 4 : l == 4 ? 2 : 1)
+         : kind == 2 ? (l <= 2 ? 2 : 1)
+                     : (l <= 2 ? 4 : l == 3 ? 2 : 1);
+}
+
+// Bytes of one scan element of each kind (for checkpoint storage).
+constexpr int elem_bytes(int kind) { return kind == 0 ? 8 : kind == 2 ? 32 : 16; }
+
+}  // namespace mmot

@@ -1,0 +1,157 @@
+// Device kernels of libmmot (templates; instantiated by k_single.hip and k_batch.hip).
+//
+// One wavefront works on one problem instance at a time (scan.hpp); a block of
+// 256 threads is four independent wavefronts.  The solve kernels run the whole
+// Gauss-Seidel iteration on the device: the l marginal updates of a sweep
+// (Alg. 1 update lines, Sec. 4.2 update formulas), the FP64 residual every
+// check_every sweeps (Alg. 1 Res line) and the FP64 objective at the end
+// (Sec. 2 Eq. mmot distance).  The batch kernel is persistent: each wavefront
+// takes the next instance from an atomic ticket until the list is exhausted.
+#pragma once
+#include <type_traits>
+
+#include "launch.hpp"
+#include "scan.hpp"
+
+namespace mmot {
+
+static constexpr int ST_OK = 0;
+static constexpr int ST_NUMERIC = -3;
+static constexpr int ST_NOT_CONVERGED = -4;
+
+template <int L, typename M>
+__device__ __forceinline__ const Disc<M> *upd_disc(const Inst *I)
+{
+    if constexpr (std::is_same<M, float>::value)
+        return &I->d32;
+    else
+        return &I->d64;
+}
+
+// Whole solve of one instance on one wavefront.
+template <int L, typename M>
+__device__ void solve_one(const Inst *__restrict__ I, const Ptrs P, const RunOpts o, Result *__restrict__ R, int lane)
+{
+    constexpr int KU = std::is_same<M, float>::value ? 0 : 1;
+    constexpr int VU = vsel(L, KU);
+    constexpr int VC = vsel(L, 3);
+    constexpr int VO = vsel(L, 2);
+    const long N = I->N;
+    double *a = P.a;
+    const double *lu = P.log_u;
+    const int flags = o.flags | P.flags;
+    const long itr_max = P.itr_cap > 0 ? P.itr_cap : o.itr_max;
+
+    if (!(flags & F_WARM)) {
+        // phi = 1/N (Alg. 1 initialisation)
+        const double a0 = -log((double)N);
+        for (long p = lane; p < (long)L * N; p += WAVE) a[p] = a0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    long it = 0;
+    double res = INFINITY;
+    int status = ST_OK;
+    bool checked = false;
+    while (it < itr_max) {
+        ++it;
+        for (int j = 0; j < L; ++j)
+            marginal_pass<L, VU, XF<M>, P_UPDATE>(I, upd_disc<L, M>(I), j, a, lu, nullptr, P.scratch, lane);
+        const bool chk = !(flags & F_NO_CHECK) &&
+                         ((o.check_every > 0 && it % o.check_every == 0) || it == itr_max);
+        if (chk) {
+            checked = true;
+            res = 0.0;
+            for (int j = 0; j < L - 1; ++j)
+                res += marginal_pass<L, VC, XF<double>, P_CHECK>(I, &I->dck, j, a, lu, nullptr, P.scratch, lane);
+            if (!(res == res)) {
+                status = ST_NUMERIC;
+                break;
+            }
+            if (res <= o.tol) break;
+        }
+    }
+    double W = 0.0;
+    if (status == ST_OK && !(flags & F_NO_OBJ)) {
+        W = marginal_pass<L, VO, DXF, P_OBJECTIVE>(I, &I->dob, L - 1, a, lu, nullptr, P.scratch, lane);
+        if (!(W == W) || W == INFINITY) status = ST_NUMERIC;
+    }
+    if (status == ST_OK && checked && o.tol >= 0.0 && !(res <= o.tol)) status = ST_NOT_CONVERGED;
+    if (lane == 0) {
+        R->W = W;
+        R->marg_err = res;
+        R->iters = it;
+        R->status = status;
+        R->l = L;
+        R->N = N;
+    }
+}
+
+template <int L, typename M>
+__global__ __launch_bounds__(64, 2) void k_solve_single(const Inst *I, Ptrs P, RunOpts o, Result *R)
+{
+    solve_one<L, M>(I, P, o, R, threadIdx.x);
+}
+
+template <typename M>
+__device__ void solve_dispatch(const Inst *I, const Ptrs P, const RunOpts o, Result *R, int lane)
+{
+    switch (I->l) {
+        case 2: solve_one<2, M>(I, P, o, R, lane); break;
+        case 3: solve_one<3, M>(I, P, o, R, lane); break;
+        case 4: solve_one<4, M>(I, P, o, R, lane); break;
+        case 5: solve_one<5, M>(I, P, o, R, lane); break;
+        case 6: solve_one<6, M>(I, P, o, R, lane); break;
+#if MMOT_BUILD_MAXL >= 7
+        case 7: solve_one<7, M>(I, P, o, R, lane); break;
+#endif
+#if MMOT_BUILD_MAXL >= 8
+        case 8: solve_one<8, M>(I, P, o, R, lane); break;
+#endif
+        default: break;
+    }
+}
+
+// Persistent batch: wavefronts pull instance tickets until none is left.
+template <typename M>
+__global__ __launch_bounds__(256, 2) void k_solve_batch(const Inst *I, const Ptrs *P, const int *order, int count,
+                                                     RunOpts o, Result *R, int *ticket)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(ticket, 1);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        if (t >= count) break;
+        const int idx = __builtin_amdgcn_readfirstlane(order[t]);
+        solve_dispatch<M>(&I[idx], P[idx], o, &R[idx], lane);
+    }
+}
+
+
+template <int L, int V, typename E, int MODE>
+__global__ __launch_bounds__(64) void k_pass(const Inst *I, Ptrs P, int j, double *result)
+{
+    const Disc<typename ET<E>::MT> *K;
+    if constexpr (MODE == P_OBJECTIVE)
+        K = &I->dob;
+    else if constexpr (std::is_same<typename ET<E>::MT, float>::value)
+        K = (const Disc<typename ET<E>::MT> *)&I->d32;
+    else
+        K = (const Disc<typename ET<E>::MT> *)&I->d64;
+    const double r = marginal_pass<L, V, E, MODE>(I, K, j, P.a, P.log_u, P.out, P.scratch, threadIdx.x);
+    if (threadIdx.x == 0 && result) result[0] = r;
+}
+
+template <int L>
+__global__ __launch_bounds__(64) void k_check_all(const Inst *I, Ptrs P, double *err)
+{
+    constexpr int VC = vsel(L, 3);
+    for (int j = 0; j < L; ++j) {
+        const double r = marginal_pass<L, VC, XF<double>, P_CHECK>(I, &I->dck, j, P.a, P.log_u, nullptr, P.scratch,
+                                                                  threadIdx.x);
+        if (threadIdx.x == 0) err[j] = r;
+    }
+}
+
+}  // namespace mmot

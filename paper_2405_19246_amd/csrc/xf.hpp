@@ -1,0 +1,173 @@
+// Device arithmetic on extended-range values (see XF in common.hpp) and on the
+// pair (value, cost-weighted value) used for the objective.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace mmot {
+
+constexpr double LN2_HI = 6.93147180369123816490e-01;  // high part, exact times small ints
+constexpr double LN2_LO = 1.90821492927058770002e-10;
+constexpr double LOG2E = 1.44269504088896338700e+00;
+
+__device__ __forceinline__ float xldexp(float m, int e) { return __builtin_amdgcn_ldexpf(m, e); }
+__device__ __forceinline__ double xldexp(double m, int e) { return __builtin_amdgcn_ldexp(m, e); }
+__device__ __forceinline__ float xmant(float m) { return __builtin_amdgcn_frexp_mantf(m); }
+__device__ __forceinline__ double xmant(double m) { return __builtin_amdgcn_frexp_mant(m); }
+__device__ __forceinline__ int xexpo(float m) { return __builtin_amdgcn_frexp_expf(m); }
+__device__ __forceinline__ int xexpo(double m) { return __builtin_amdgcn_frexp_exp(m); }
+__device__ __forceinline__ float xexp_r(double r, float) { return expf((float)r); }
+__device__ __forceinline__ double xexp_r(double r, double) { return exp(r); }
+__device__ __forceinline__ double xlog_m(float m) { return (double)logf(m); }
+__device__ __forceinline__ double xlog_m(double m) { return log(m); }
+
+template <typename M>
+__device__ __forceinline__ XF<M> xzero() { return {M(0), XF_ZERO_E}; }
+template <typename M>
+__device__ __forceinline__ XF<M> xone() { return {M(0.5), 1}; }
+
+template <typename M>
+__device__ __forceinline__ XF<M> xadd(XF<M> a, XF<M> b)
+{
+    const int e = max(a.e, b.e);
+    const M m = xldexp(a.m, a.e - e) + xldexp(b.m, b.e - e);
+    return {xmant(m), e + xexpo(m)};
+}
+
+template <typename M>
+__device__ __forceinline__ XF<M> xmul(XF<M> a, XF<M> b)
+{
+    return {a.m * b.m, max(a.e + b.e, XF_ZERO_E)};
+}
+
+// exp(a) for a natural log a (FP64): round a / ln 2 to an integer k, reduce with
+// a two-part ln 2, exponentiate the remainder in the mantissa precision.
+template <typename M>
+__device__ __forceinline__ XF<M> xfrom_log(double a)
+{
+    if (!(a > -1.0e15)) {
+        if (a != a) return {M(NAN), 0};
+        return xzero<M>();
+    }
+    if (!(a < 1.0e15)) return {M(NAN), 0};
+    const double k = rint(a * LOG2E);
+    double r = fma(-k, LN2_HI, a);
+    r = fma(-k, LN2_LO, r);
+    const M m = xexp_r(r, M(0));
+    return {xmant(m), (int)k + xexpo(m)};
+}
+
+// exp(a) as a discount factor with a hi + lo mantissa (see XG).
+template <typename M>
+__device__ __forceinline__ XG<M> xg_from_log(double a)
+{
+    if (!(a > -1.0e15)) return {M(0), M(0), XF_ZERO_E, 0};
+    const double k = rint(a * LOG2E);
+    double r = fma(-k, LN2_HI, a);
+    r = fma(-k, LN2_LO, r);
+    const double v = exp(r);
+    const int ev = xexpo(v);
+    const double vm = xldexp(v, -ev);  // in [0.5, 1)
+    const M hi = (M)vm;
+    const M lo = (M)(vm - (double)hi);
+    return {hi, lo, (int)k + ev, 0};
+}
+
+// x times a discount factor.
+template <typename M>
+__device__ __forceinline__ XF<M> xmulg(XF<M> x, XG<M> g)
+{
+    if constexpr (sizeof(M) == 4)
+        return {fmaf(x.m, g.hi, x.m * g.lo), max(x.e + g.e, XF_ZERO_E)};
+    else
+        return {x.m * g.hi, max(x.e + g.e, XF_ZERO_E)};
+}
+
+// Natural log of an extended value, FP64.
+template <typename M>
+__device__ __forceinline__ double xto_log(XF<M> x)
+{
+    if (x.m == M(0)) return -INFINITY;
+    const double e = (double)x.e;
+    return fma(e, LN2_HI, fma(e, LN2_LO, xlog_m(x.m)));
+}
+
+template <typename M>
+__device__ __forceinline__ double xto_double(XF<M> x)
+{
+    return xldexp((double)x.m, x.e);
+}
+
+// ---- cross-lane moves ----
+__device__ __forceinline__ float rlane(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ int rlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double rlane(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---- element kinds used by the scans ----
+// XF<M>: plain value.  DXF: (value, cost-weighted value) for the objective.
+struct DXF {
+    XF<double> v;
+    XF<double> w;
+};
+
+template <typename E>
+struct ET;
+
+template <typename M>
+struct ET<XF<M>> {
+    using MT = M;
+    using El = XF<M>;
+    static __device__ __forceinline__ El zero() { return xzero<M>(); }
+    static __device__ __forceinline__ El one() { return xone<M>(); }
+    static __device__ __forceinline__ El add(El a, El b) { return xadd(a, b); }
+    // times a scalar value (a product of scaling factors)
+    static __device__ __forceinline__ El scale(El a, XF<M> s) { return xmul(a, s); }
+    // across p gaps at level k: times g(k)^p; the weighted count p * k (l - k) is unused
+    static __device__ __forceinline__ El disc(El a, XG<M> gp, double) { return xmulg(a, gp); }
+    static __device__ __forceinline__ El prod(El a, El b) { return xmul(a, b); }
+    static __device__ __forceinline__ El shup(El a, int d) { return {__shfl_up(a.m, d), __shfl_up(a.e, d)}; }
+    static __device__ __forceinline__ El shdn(El a, int d) { return {__shfl_down(a.m, d), __shfl_down(a.e, d)}; }
+    static __device__ __forceinline__ El rl(El a, int l) { return {rlane(a.m, l), rlane(a.e, l)}; }
+};
+
+__device__ __forceinline__ XF<double> xfrom_small(double c)
+{
+    return {xmant(c), c == 0.0 ? XF_ZERO_E : xexpo(c)};
+}
+
+template <>
+struct ET<DXF> {
+    using MT = double;
+    using El = DXF;
+    using P = ET<XF<double>>;
+    static __device__ __forceinline__ El zero() { return {xzero<double>(), xzero<double>()}; }
+    static __device__ __forceinline__ El one() { return {xone<double>(), xzero<double>()}; }
+    static __device__ __forceinline__ El add(El a, El b) { return {xadd(a.v, b.v), xadd(a.w, b.w)}; }
+    static __device__ __forceinline__ El scale(El a, XF<double> s) { return {xmul(a.v, s), xmul(a.w, s)}; }
+    // crossing p gaps with k(l-k) separated pairs each adds p*k(l-k) times the
+    // value to the weighted part, then both parts take the factor g(k)^p
+    static __device__ __forceinline__ El disc(El a, XG<double> gp, double pc)
+    {
+        const XF<double> w = (pc == 0.0) ? a.w : xadd(a.w, xmul(a.v, xfrom_small(pc)));
+        return {xmulg(a.v, gp), xmulg(w, gp)};
+    }
+    static __device__ __forceinline__ El prod(El a, El b)
+    {
+        return {xmul(a.v, b.v), xadd(xmul(a.v, b.w), xmul(a.w, b.v))};
+    }
+    static __device__ __forceinline__ El shup(El a, int d) { return {P::shup(a.v, d), P::shup(a.w, d)}; }
+    static __device__ __forceinline__ El shdn(El a, int d) { return {P::shdn(a.v, d), P::shdn(a.w, d)}; }
+    static __device__ __forceinline__ El rl(El a, int l) { return {P::rl(a.v, l), P::rl(a.w, l)}; }
+};
+
+}  // namespace mmot
