@@ -41,6 +41,7 @@ def _units():
     units.append((os.path.join(HERE, "k_batch.hip"), "k_batch.o", []))
     units.append((os.path.join(HERE, "api.cpp"), "api.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "serve.cpp"), "serve.o", ["-x", "hip"]))
+    units.append((os.path.join(HERE, "tables.cpp"), "tables.o", []))
     return units
 
 

@@ -124,12 +124,14 @@ __device__ __forceinline__ void store_elem(void *base, long idx, int lane_ok, E 
     if (lane_ok) reinterpret_cast<E *>(base)[idx] = x;
 }
 
-// Wave-wide FP64 sum.
+// Wave-wide FP64 sum, the same value in every lane.  (A butterfly leaves each
+// lane with its own summation order, and a stopping test on per-lane sums
+// could split the wavefront; lane 0's sum is broadcast.)
 __device__ __forceinline__ double wave_sum(double x)
 {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-    return x;
+    return rlane(x, 0);
 }
 
 __device__ __forceinline__ XF<double> wave_sum_xf(XF<double> x)
@@ -139,7 +141,7 @@ __device__ __forceinline__ XF<double> wave_sum_xf(XF<double> x)
         const XF<double> o = {__shfl_xor(x.m, d), __shfl_xor(x.e, d)};
         x = xadd(x, o);
     }
-    return x;
+    return {rlane(x.m, 0), rlane(x.e, 0)};
 }
 
 // One marginal pass over an instance on one wavefront.

@@ -6,6 +6,7 @@
 
 #include "common.hpp"
 #include "mmot.h"
+#include "tables.hpp"
 
 namespace mmot {
 
@@ -20,8 +21,6 @@ struct BatchBuffers {
 namespace rt {
 extern thread_local std::string g_err;
 int fail(int code, const std::string &msg);
-Inst make_inst(int l, int64_t N, double h, double eps);
-size_t scratch_bytes(int l, int64_t N, int precision);
 int check_shape(int l, int64_t N, double h, double eps);
 int check_opts(const mmot_opts *o);
 }  // namespace rt

@@ -1,0 +1,82 @@
+// Host-side tables of libmmot: discount factors, device descriptors and
+// checkpoint sizes.  Plain C++ (no HIP calls), shared by the runtime and the
+// serving loop.
+#include "tables.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace mmot {
+namespace rt {
+
+namespace {
+constexpr double H_LN2_HI = 6.93147180369123816490e-01;
+constexpr double H_LN2_LO = 1.90821492927058770002e-10;
+constexpr double H_LOG2E = 1.44269504088896338700e+00;
+
+// exp(lognat) as a discount factor with a hi + lo mantissa.
+template <typename M>
+XG<M> host_xg(double lognat)
+{
+    if (!(lognat > -1.0e15)) return {M(0), M(0), XF_ZERO_E, 0};
+    const double k = std::nearbyint(lognat * H_LOG2E);
+    double r = std::fma(-k, H_LN2_HI, lognat);
+    r = std::fma(-k, H_LN2_LO, r);
+    int ex = 0;
+    const double vm = std::frexp(std::exp(r), &ex);
+    const M hi = (M)vm;
+    const M lo = (M)(vm - (double)hi);
+    return {hi, lo, (int32_t)k + ex, 0};
+}
+}  // namespace
+
+// Discount tables for scans of lane width V: g(k) = lambda^{k (l - k)},
+// ln g(k) = -k (l - k) h / eps, for k = 0..l-1 (k summed marginals placed).
+template <typename M>
+void fill_disc(Disc<M> &d, int l, double hoe, int V)
+{
+    std::memset(&d, 0, sizeof d);
+    d.V = V;
+    for (int k = 0; k < MAXL; ++k) {
+        const double lg = (k < l) ? -(double)(k * (l - k)) * hoe : 0.0;
+        d.g1[k] = host_xg<M>(lg);
+        for (int s = 0; s < 6; ++s) d.gstep[k][s] = host_xg<M>(lg * (double)(V << s));
+        for (int t = 0; t < MAXV; ++t) d.gfix[k][t] = host_xg<M>(lg * (double)(t + 1));
+        d.lgV[k] = lg * (double)V;
+    }
+    for (int k = 0; k <= MAXL; ++k) d.ck[k] = (k <= l) ? (double)(k * (l - k)) : 0.0;
+}
+
+Inst make_inst(int l, int64_t N, double h, double eps)
+{
+    Inst I;
+    std::memset(&I, 0, sizeof I);
+    I.N = N;
+    I.l = l;
+    I.h = h;
+    I.hoe = h / eps;
+    fill_disc<float>(I.d32, l, I.hoe, vsel(l, 0));
+    fill_disc<double>(I.d64, l, I.hoe, vsel(l, 1));
+    fill_disc<double>(I.dob, l, I.hoe, vsel(l, 2));
+    fill_disc<double>(I.dck, l, I.hoe, vsel(l, 3));
+    return I;
+}
+
+// Checkpoint bytes for one instance: the largest over the passes it runs.
+size_t scratch_bytes(int l, int64_t N, int precision)
+{
+    const int D1 = (1 << (l - 1)) - 1;
+    size_t best = 0;
+    const int kinds[3] = {precision == MMOT_FP32 ? 0 : 1, 2, 3};
+    for (int kind : kinds) {
+        const int64_t CH = (int64_t)WAVE * vsel(l, kind);
+        const int64_t C = (N + CH - 1) / CH;
+        best = std::max(best, (size_t)C * (size_t)D1 * (size_t)elem_bytes(kind));
+    }
+    return (best + 255) & ~(size_t)255;
+}
+
+
+}  // namespace rt
+}  // namespace mmot
