@@ -4,17 +4,20 @@
 Workload (one "step"): a batch of seeded synthetic instances of the l = 4,
 N = 1000, eps = 1e-2 problem (3-component Gaussian-mixture marginals on a
 uniform grid of [0, 1], +1e-3 floor, normalised), each solved to the FP64
-marginal error Res <= 1e-6 with FP32 scans, FP64 checks every 10 sweeps and an
-FP64 objective -- all of it in ONE persistent launch (mmot_solve_batch).
-Inputs are resident in device memory before the timed region.
+marginal error Res <= 1e-6 with FP32 scans and an FP64 objective
+(mmot_solve_batch): rounds of the register-resident sweep kernel (one
+workgroup per instance) and the FP64 residual-check kernel, checks taken when
+the sweeps' own error estimate asks for one.  Inputs are resident in device
+memory before the timed region.
 
 value = sum over instances of l * N * sweeps, divided by the wall time of the
 K timed steps (bracketed by device synchronisation).
 
-Extra fields: the same batch in FP64 to Res <= 1e-8; the plain
-one-solve-per-launch form at the same accuracy and the batched speed-up; a
-short continuous-batching serving run with p50/p99 latency; the roofline of
-the batch kernel; and the oracle timed on host cores on a bounded sample.
+Extra fields: the same batch in FP64 to Res <= 1e-8; the same batch on the
+extended-range solver (one wavefront per instance); the plain
+one-solve-per-call form and the batched speed-up; a short continuous-batching
+serving run with p50/p99 latency; the roofline of the sweep kernel; and the
+oracle timed on host cores on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--instances B]
 """
@@ -34,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "l4_n1000_eps0.01"
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
 
 
 def kernel_source_sha1() -> str:
@@ -76,7 +80,7 @@ def units_of(res):
 
 
 def traffic_entry(sha: str):
-    path = os.path.join(ROOT, "profiles", "traffic_k_solve_batch_l4_n1000.json")
+    path = os.path.join(ROOT, "profiles", "traffic_l4_n1000.json")
     if not os.path.exists(path):
         return None
     try:
@@ -129,8 +133,8 @@ def main():
     tol32, tol64 = 1e-6, 1e-8
     batch = make_batch(args.instances, dev)
 
-    def step(prec, tol):
-        return mmot.solve_batch(batch, precision=prec, tol=tol, itr_max=20000, check_every=10)
+    def step(prec, tol, fast=True):
+        return mmot.solve_batch(batch, precision=prec, tol=tol, itr_max=20000, check_every=0, fast=fast)
 
     for _ in range(args.warmup):
         step(mmot.FP32, tol32)
@@ -138,27 +142,47 @@ def main():
     t0 = time.perf_counter()
     units = 0.0
     kern_ms = []
+    timings = []
     res = None
     for _ in range(args.steps):
         res = step(mmot.FP32, tol32)
         units += units_of(res)
         kern_ms.append(mmot.last_batch_kernel_ms())
+        timings.append(mmot.last_batch_timing())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     value = units / wall
     ok = all(r["status"] == 0 and r["marg_err"] <= tol32 for r in res)
     iters = np.array([r["iters"] for r in res])
 
-    per_launch_units = units / args.steps
-    k_ms = float(np.mean(kern_ms))
-    bytes_per_unit = (4 + 1) * 8  # read l-1 potential rows and log u_j, write a_j: (l + 1) FP64 per update
-    achieved = per_launch_units * bytes_per_unit / (k_ms / 1e3) / 1e9
+    # roofline of the dominant kernel: algorithmic FP32 flops of the gap-form
+    # recurrences per marginal-position update (l = 4: 2 * (3^3 - 1) + 2^3 = 60
+    # multiply-adds = 120 flops) over its average launch duration (HIP events
+    # around each launch on the batch's stream).  The register-resident sweep
+    # kernel dominates when it runs; otherwise the extended-range batch kernel
+    # (one launch per step) does.
+    flops_per_unit = 2 * (3 ** 3 - 1) * 2 + 2 ** 3 * 2
+    sweep_launches = sum(t["sweep_launches"] for t in timings)
+    if sweep_launches > 0:
+        kname = "k_fast_sweep<4,4,float>"
+        avg_ms = sum(t["sweep_ms"] for t in timings) / sweep_launches
+        units_per_launch = sum(t["sweep_units"] for t in timings) / sweep_launches
+        launches = sweep_launches
+    else:
+        kname = "k_solve_batch<float>"
+        avg_ms = sum(t["other_ms"] for t in timings) / args.steps
+        units_per_launch = units / args.steps
+        launches = args.steps
+    achieved = units_per_launch * flops_per_unit / (avg_ms / 1e3) / 1e12
     sha = kernel_source_sha1()
     tr = traffic_entry(sha)
-    roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
+    roofline = dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / PEAK_FP32_TFLOPS,
                     traffic=(tr["hbm_bytes_per_launch"] if tr else None),
-                    kernel="k_solve_batch<float>", kernel_ms=k_ms, bytes_per_unit=bytes_per_unit,
-                    units_per_launch=per_launch_units)
+                    kernel=kname, avg_launch_ms=avg_ms, launches=launches,
+                    flops_per_unit=flops_per_unit, units_per_launch=units_per_launch,
+                    check_ms=sum(t["check_ms"] for t in timings) / args.steps,
+                    rounds=[t["rounds"] for t in timings], batch_ms=float(np.mean(kern_ms)))
 
     out = {
         "metric": "l*N*Sinkhorn-iters/sec at fixed marginal error (Res<=1e-6, FP64-checked)",
@@ -176,7 +200,9 @@ def main():
         "config": {"workload": "%s: batch of %d instances, l=4, N=1000, eps=1e-2, FP32 scans to Res<=1e-6"
                                % (WORKLOAD, args.instances),
                    "l": 4, "N": 1000, "eps": 0.01, "instances": args.instances, "tol": tol32,
-                   "check_every": 10, "parallelism": "one wavefront per instance, persistent launch"},
+                   "check_every": 0,
+                   "parallelism": ("one workgroup (4 wavefronts) per instance, rounds of sweep and check kernels"
+                                   if sweep_launches > 0 else "one wavefront per instance, persistent launch")},
         "all_converged": ok,
         "sweeps": {"min": int(iters.min()), "median": float(np.median(iters)), "max": int(iters.max())},
         "roofline": roofline,
@@ -188,10 +214,15 @@ def main():
         out["fp64"] = dict(value=units_of(r64) / t64, tol=tol64, seconds=t64,
                            all_converged=all(r["status"] == 0 for r in r64),
                            kernel_ms=mmot.last_batch_kernel_ms())
-        # plain form: one solve per launch, same accuracy, a subset of the batch
+        # the extended-range solver on the same batch (one wavefront per instance)
+        (rx, tx) = timed(lambda: step(mmot.FP32, tol32, fast=False))
+        out["extended_range_solver"] = dict(value=units_of(rx) / tx, seconds=tx,
+                                            all_converged=all(r["status"] == 0 for r in rx),
+                                            speedup_of_fast_path=value / (units_of(rx) / tx))
+        # plain form: one solve per call, same accuracy, a subset of the batch
         nplain = min(16, args.instances)
         plans = [mmot.Plan(4, 1000, batch[i]["h"], batch[i]["eps"], precision=mmot.FP32, tol=tol32,
-                           itr_max=20000, check_every=10) for i in range(nplain)]
+                           itr_max=20000, check_every=0) for i in range(nplain)]
 
         def plain():
             return [plans[i].solve(batch[i]["log_u"], batch[i]["log_phi"])[1] for i in range(nplain)]
@@ -215,7 +246,7 @@ def main():
                 return None
             return us[i % len(us)], h0, e0, float(arr[i])
 
-        st = mmot.serve(gen, precision=mmot.FP32, tol=tol32, itr_max=20000, check_every=10, max_slots=2048,
+        st = mmot.serve(gen, precision=mmot.FP32, tol=tol32, itr_max=20000, check_every=0, max_slots=2048,
                         block_sweeps=100, hbm_budget_bytes=16 << 30)
         out["serve"] = dict(offered_req_per_s=rate, seconds_of_arrivals=dur, requests=int(len(arr)),
                             completed=st["completed"], p50_latency_s=st["p50_latency"],

@@ -64,8 +64,15 @@ typedef struct {
 /* Stopping rule of Alg. 1: stop after itr_max sweeps or once Res <= tol, where
  * Res = sum_{j < l} || phi_j * (K x_{q != j} phi_q) - u_j ||_1 (the last marginal
  * is exact after its own update) is evaluated in FP64 after every check_every-th
- * sweep.  tol < 0 never stops early.  flags: MMOT_FLAG_WARM_START keeps the
- * potentials passed in instead of starting from phi = 1/N (Alg. 1 init). */
+ * sweep (check_every > 0), after the last sweep, and whenever the sweep's own
+ * estimate -- the marginal errors its updates removed, sum over j < l-1 of
+ * sum_y u_j(y) |phi_j,old(y) / phi_j,new(y) - 1| -- falls below tol * f, where f
+ * starts at 1 and halves after each such check that does not reach tol.
+ * tol < 0 never stops early (and never uses the estimate).
+ * flags: MMOT_FLAG_WARM_START keeps the potentials passed in instead of
+ * starting from phi = 1/N (Alg. 1 init); MMOT_FLAG_NO_FAST runs every solve on
+ * the extended-range solver (one wavefront per solve) instead of the
+ * register-resident one (one workgroup per solve, taken when N fits it). */
 typedef struct {
     double tol;
     int64_t itr_max;
@@ -74,6 +81,7 @@ typedef struct {
 } mmot_opts;
 
 #define MMOT_FLAG_WARM_START 1
+#define MMOT_FLAG_NO_FAST 2
 
 /* Per-solve outcome. */
 typedef struct {
@@ -159,11 +167,26 @@ typedef struct {
 int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_t precision, const mmot_opts *o,
                      void *hip_stream, mmot_result *res);
 
-/* Device time in milliseconds of the last persistent batch launch (the kernel
- * alone, between two HIP events recorded on its stream around the launch; the
- * ticket reset and descriptor copies are outside).  Covers mmot_solve_batch and
- * the server's rounds.  *ms: host.  MMOT_ERR_STATE before the first launch. */
+/* Device time in milliseconds of the last mmot_solve_batch call: from a HIP
+ * event recorded on its stream before its first kernel to one after its last
+ * (descriptor uploads before, the result copy after are outside; the host
+ * round trips between rounds of the register-resident path are inside).
+ * *ms: host.  MMOT_ERR_STATE before the first call. */
 int mmot_last_batch_kernel_ms(double *ms);
+
+/* Breakdown of the last mmot_solve_batch call, from HIP events around each
+ * kernel launch on its stream. */
+typedef struct {
+    double total_ms;        /* as mmot_last_batch_kernel_ms */
+    double sweep_ms;        /* sum over the sweep-kernel launches (register-resident path) */
+    double check_ms;        /* sum over the FP64 check-kernel launches */
+    double other_ms;        /* extended-range solver launches and the objective kernel */
+    double sweep_units;     /* l * N * sweeps done by the sweep-kernel launches */
+    int32_t sweep_launches; /* number of sweep-kernel launches */
+    int32_t rounds;         /* sweep + check rounds */
+} mmot_batch_timing;
+
+int mmot_last_batch_timing(mmot_batch_timing *t);
 
 /* ---------------- serving (continuous batching) ---------------- */
 

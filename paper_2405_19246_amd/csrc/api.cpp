@@ -63,6 +63,8 @@ struct mmot_plan {
     mmot_problem p;
     mmot_opts o;
     hipStream_t s;
+    Inst hI;
+    mutable BatchBuffers bb = {};  // one-instance batch for the solve entry points
     Inst *dI = nullptr;
     void *scratch = nullptr;
     size_t scratch_size = 0;
@@ -93,11 +95,13 @@ int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_
     pl->o = oo;
     pl->s = (hipStream_t)hip_stream;
     const Inst I = make_inst(p->l, p->N, p->h, p->eps);
+    pl->hI = I;
     pl->scratch_size = scratch_bytes(p->l, p->N, p->precision);
     hipError_t e = hipMalloc((void **)&pl->dI, sizeof(Inst));
     if (e == hipSuccess) e = hipMalloc(&pl->scratch, std::max<size_t>(pl->scratch_size, 256));
     if (e == hipSuccess) e = hipMalloc((void **)&pl->dR, sizeof(Result));
     if (e == hipSuccess) e = hipMalloc((void **)&pl->dtmp, sizeof(double) * MAXL);
+    if (e == hipSuccess) e = batch_buffers_alloc(&pl->bb, 1);
     if (e == hipSuccess) e = hipMemcpy(pl->dI, &I, sizeof(Inst), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         mmot_plan_destroy(pl);
@@ -111,7 +115,8 @@ int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_
 int mmot_plan_footprint(const mmot_plan_t *pl, size_t *device_bytes)
 {
     if (!pl || !device_bytes) return fail(MMOT_ERR_INVALID, "NULL argument");
-    *device_bytes = sizeof(Inst) + pl->scratch_size + sizeof(Result) + sizeof(double) * MAXL +
+    *device_bytes = 2 * sizeof(Inst) + pl->scratch_size + 2 * sizeof(Result) + sizeof(double) * MAXL +
+                    sizeof(Ptrs) + 3 * sizeof(int) + sizeof(Track) +
                     2 * sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N;
     return MMOT_OK;
 }
@@ -120,6 +125,7 @@ int mmot_plan_destroy(mmot_plan_t *pl)
 {
     if (!pl) return MMOT_OK;
     if (pl->dI) (void)hipFree(pl->dI);
+    batch_buffers_free(&pl->bb);
     if (pl->scratch) (void)hipFree(pl->scratch);
     if (pl->dR) (void)hipFree(pl->dR);
     if (pl->dtmp) (void)hipFree(pl->dtmp);
@@ -131,27 +137,22 @@ int mmot_marginal_product(const mmot_plan_t *pl, int32_t j, const double *log_ph
 {
     if (!pl || !log_phi || !log_J) return fail(MMOT_ERR_INVALID, "NULL argument");
     if (j < 0 || j >= pl->p.l) return fail(MMOT_ERR_INVALID, "j out of range");
-    Ptrs P = {nullptr, const_cast<double *>(log_phi), log_J, pl->scratch, 0, 0, 0};
+    Ptrs P = {nullptr, const_cast<double *>(log_phi), log_J, pl->scratch, 0, 0, 0, 0};
     HIPCHK(launch_pass(pl->p.l, pl->p.precision, 0, pl->dI, P, j, nullptr, pl->s));
-    return MMOT_OK;
-}
-
-static int read_result(const mmot_plan_t *pl, Result *R)
-{
-    HIPCHK(hipMemcpyAsync(R, pl->dR, sizeof(Result), hipMemcpyDeviceToHost, pl->s));
-    HIPCHK(hipStreamSynchronize(pl->s));
     return MMOT_OK;
 }
 
 int mmot_marginal_errors(const mmot_plan_t *pl, const double *log_u, const double *log_phi, double *err)
 {
     if (!pl || !log_u || !log_phi || !err) return fail(MMOT_ERR_INVALID, "NULL argument");
-    Ptrs P = {log_u, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0};
+    Ptrs P = {log_u, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
     HIPCHK(launch_pass(pl->p.l, MMOT_FP64, 2, pl->dI, P, 0, pl->dtmp, pl->s));
     HIPCHK(hipMemcpyAsync(err, pl->dtmp, sizeof(double) * pl->p.l, hipMemcpyDeviceToHost, pl->s));
     HIPCHK(hipStreamSynchronize(pl->s));
     return MMOT_OK;
 }
+
+static int plan_path(const mmot_plan_t *pl) { return (pl->o.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0; }
 
 int mmot_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_phi, int64_t n_sweeps,
                        double *marg_err)
@@ -159,13 +160,12 @@ int mmot_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_p
     if (!pl || !log_u || !log_phi) return fail(MMOT_ERR_INVALID, "NULL argument");
     if (n_sweeps < 0) return fail(MMOT_ERR_INVALID, "n_sweeps must be >= 0");
     if (n_sweeps > 0) {
-        RunOpts o = {-1.0, n_sweeps, 0, F_WARM | F_NO_OBJ | (marg_err ? 0 : F_NO_CHECK)};
-        Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, 0};
-        HIPCHK(launch_solve_single(pl->p.l, pl->p.precision, pl->dI, P, o, pl->dR, pl->s));
-        if (!marg_err) return MMOT_OK;
+        RunOpts o = {-1.0, n_sweeps, 0, F_WARM | F_NO_OBJ | (marg_err ? 0 : F_NO_CHECK) | plan_path(pl)};
+        Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, F_WARM, 0};
         Result R;
-        int rc = read_result(pl, &R);
+        int rc = batch_launch(&pl->hI, &P, 1, pl->p.precision, o, pl->s, &R, &pl->bb);
         if (rc) return rc;
+        if (!marg_err) return MMOT_OK;
         *marg_err = R.marg_err;
         if (R.status == MMOT_ERR_NUMERIC || !std::isfinite(R.marg_err)) return fail(MMOT_ERR_NUMERIC, "non-finite residual");
         return MMOT_OK;
@@ -183,11 +183,11 @@ int mmot_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_p
 int mmot_solve(const mmot_plan_t *pl, const double *log_u, double *log_phi, mmot_result *res)
 {
     if (!pl || !log_u || !log_phi || !res) return fail(MMOT_ERR_INVALID, "NULL argument");
-    RunOpts o = {pl->o.tol, pl->o.itr_max, pl->o.check_every, (pl->o.flags & MMOT_FLAG_WARM_START) ? F_WARM : 0};
-    Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, 0};
-    HIPCHK(launch_solve_single(pl->p.l, pl->p.precision, pl->dI, P, o, pl->dR, pl->s));
+    const int warm = (pl->o.flags & MMOT_FLAG_WARM_START) ? F_WARM : 0;
+    RunOpts o = {pl->o.tol, pl->o.itr_max, pl->o.check_every, plan_path(pl)};
+    Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, warm, 0};
     Result R;
-    int rc = read_result(pl, &R);
+    int rc = batch_launch(&pl->hI, &P, 1, pl->p.precision, o, pl->s, &R, &pl->bb);
     if (rc) return rc;
     static_assert(sizeof(Result) == sizeof(mmot_result), "result layout");
     std::memcpy(res, &R, sizeof R);
@@ -202,7 +202,7 @@ int mmot_solve(const mmot_plan_t *pl, const double *log_u, double *log_phi, mmot
 int mmot_objective(const mmot_plan_t *pl, const double *log_phi, double *W)
 {
     if (!pl || !log_phi || !W) return fail(MMOT_ERR_INVALID, "NULL argument");
-    Ptrs P = {nullptr, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0};
+    Ptrs P = {nullptr, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
     HIPCHK(launch_pass(pl->p.l, MMOT_FP64, 3, pl->dI, P, pl->p.l - 1, pl->dtmp, pl->s));
     HIPCHK(hipMemcpyAsync(W, pl->dtmp, sizeof(double), hipMemcpyDeviceToHost, pl->s));
     HIPCHK(hipStreamSynchronize(pl->s));
@@ -218,33 +218,22 @@ namespace {
 // Grow-only device arena for batch launches (one per process, serialised).
 struct BatchArena {
     std::mutex mu;
-    Inst *dI = nullptr;
-    Ptrs *dP = nullptr;
-    int *dorder = nullptr;
-    Result *dR = nullptr;
-    int *dticket = nullptr;
+    BatchBuffers bb = {};
     char *scratch = nullptr;
     size_t cap_inst = 0, cap_scratch = 0;
 
     int reserve(size_t count, size_t scratch_total)
     {
         if (count > cap_inst) {
-            if (dI) (void)hipFree(dI);
-            if (dP) (void)hipFree(dP);
-            if (dorder) (void)hipFree(dorder);
-            if (dR) (void)hipFree(dR);
-            dI = nullptr; dP = nullptr; dorder = nullptr; dR = nullptr;
+            batch_buffers_free(&bb);
             cap_inst = 0;
-            size_t c = std::max<size_t>(count, 64);
-            if (hipMalloc((void **)&dI, sizeof(Inst) * c) != hipSuccess ||
-                hipMalloc((void **)&dP, sizeof(Ptrs) * c) != hipSuccess ||
-                hipMalloc((void **)&dorder, sizeof(int) * c) != hipSuccess ||
-                hipMalloc((void **)&dR, sizeof(Result) * c) != hipSuccess)
+            const size_t c = std::max<size_t>(count, 64);
+            if (batch_buffers_alloc(&bb, c) != hipSuccess) {
+                batch_buffers_free(&bb);
                 return fail(MMOT_ERR_NOMEM, "batch descriptor allocation failed");
+            }
             cap_inst = c;
         }
-        if (!dticket && hipMalloc((void **)&dticket, sizeof(int)) != hipSuccess)
-            return fail(MMOT_ERR_NOMEM, "ticket allocation failed");
         if (scratch_total > cap_scratch) {
             if (scratch) (void)hipFree(scratch);
             scratch = nullptr;
@@ -263,6 +252,39 @@ BatchArena g_batch;
 std::mutex g_time_mu;
 hipEvent_t g_ev0 = nullptr, g_ev1 = nullptr;
 double g_last_kernel_ms = -1.0;
+mmot_batch_timing g_last_timing = {};
+
+// Events around individual launches of one timed batch (grow-only pool).
+struct LaunchTimer {
+    std::vector<hipEvent_t> pool;
+    struct Span {
+        int kind;  // 0 sweep, 1 check, 2 other
+        int e0, e1;
+    };
+    std::vector<Span> spans;
+    bool on = false;
+
+    hipError_t begin(int kind, hipStream_t s, int *slot)
+    {
+        *slot = -1;
+        if (!on) return hipSuccess;
+        const int need = 2 * ((int)spans.size() + 1);
+        while ((int)pool.size() < need) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            pool.push_back(e);
+        }
+        const int i = 2 * (int)spans.size();
+        spans.push_back({kind, i, i + 1});
+        *slot = (int)spans.size() - 1;
+        return hipEventRecord(pool[i], s);
+    }
+    hipError_t end(int slot, hipStream_t s) { return slot < 0 ? hipSuccess : hipEventRecord(pool[spans[slot].e1], s); }
+};
+LaunchTimer g_timer;
+
+constexpr int ST_OK_HOST = 0;
 
 // Estimated work of one solve: scan cost per position grows like l 2^(l-1),
 // sweeps grow as eps shrinks.  Only used to order the work queue.
@@ -275,34 +297,223 @@ double est_cost(int l, int64_t N, double eps)
 
 namespace mmot {
 
-// Shared by mmot_solve_batch and the server: enqueue one persistent launch.
+hipError_t batch_buffers_alloc(BatchBuffers *bb, size_t c)
+{
+    *bb = {};
+    hipError_t e = hipMalloc((void **)&bb->dI, sizeof(Inst) * c);
+    if (e == hipSuccess) e = hipMalloc((void **)&bb->dP, sizeof(Ptrs) * c);
+    if (e == hipSuccess) e = hipMalloc((void **)&bb->dorder, sizeof(int) * 2 * c);
+    if (e == hipSuccess) e = hipMalloc((void **)&bb->dR, sizeof(Result) * c);
+    if (e == hipSuccess) e = hipMalloc((void **)&bb->dticket, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&bb->dT, sizeof(Track) * c);
+    return e;
+}
+
+void batch_buffers_free(BatchBuffers *bb)
+{
+    if (bb->dI) (void)hipFree(bb->dI);
+    if (bb->dP) (void)hipFree(bb->dP);
+    if (bb->dorder) (void)hipFree(bb->dorder);
+    if (bb->dR) (void)hipFree(bb->dR);
+    if (bb->dticket) (void)hipFree(bb->dticket);
+    if (bb->dT) (void)hipFree(bb->dT);
+    *bb = {};
+}
+
+// Shared by mmot_solve_batch, the plan entry points and the server.
+//   1. instances the register-resident path does not take: one persistent
+//      launch of the extended-range solver (one wavefront per instance);
+//   2. the others, grouped by l: rounds of the sweep kernel (runs each solve
+//      until a residual check is due) and the FP64 check kernel, until no
+//      solve is left sweeping; solves handed to the extended-range solver
+//      mid-way resume there in one more persistent launch;
+//   3. the objective of the fast-path solves, one wavefront each.
 int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const RunOpts &o, hipStream_t s,
-                 Result *hR, BatchBuffers *bb)
+                 Result *hR, BatchBuffers *bb, bool timed)
 {
     if (count <= 0) return MMOT_OK;
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
+    const int flags = o.flags;
     std::vector<double> cost(count);
     for (int i = 0; i < count; ++i) cost[i] = est_cost(hI[i].l, hI[i].N, hI[i].h / hI[i].hoe);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    auto by_cost = [&](std::vector<int> &v) {
+        std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    };
+    std::vector<int> robust, group[MAXL + 1];
+    for (int i = 0; i < count; ++i) {
+        if (!(flags & F_NO_FAST) && fast_eligible(hI[i], precision)) group[hI[i].l].push_back(i);
+        else robust.push_back(i);
+    }
+    by_cost(robust);
+    // dorder: [robust | group 2 | group 3 | ...], then the second half for resumed and objective lists
+    std::vector<int> order;
+    order.reserve(2 * (size_t)count);
+    order.insert(order.end(), robust.begin(), robust.end());
+    int goff[MAXL + 1] = {0}, gmaxN[MAXL + 1] = {0};
+    for (int l = 2; l <= MAXL; ++l) {
+        by_cost(group[l]);
+        goff[l] = (int)order.size();
+        order.insert(order.end(), group[l].begin(), group[l].end());
+        for (int i : group[l]) gmaxN[l] = std::max<int>(gmaxN[l], (int)hI[i].N);
+    }
     HIPCHK(hipMemcpyAsync(bb->dI, hI, sizeof(Inst) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(bb->dP, hP, sizeof(Ptrs) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(bb->dorder, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
-    const int waves = count;
-    const int blocks = std::max(1, std::min((waves + 3) / 4, 4096));
-    std::lock_guard<std::mutex> lk(g_time_mu);
-    if (!g_ev0) {
-        HIPCHK(hipEventCreate(&g_ev0));
-        HIPCHK(hipEventCreate(&g_ev1));
+    const bool any_fast = (int)robust.size() < count;
+    std::vector<Track> hT;
+    if (any_fast) {
+        hT.resize(count);
+        for (int i = 0; i < count; ++i) {
+            const int64_t itr = hP[i].itr_cap > 0 ? hP[i].itr_cap : o.itr_max;
+            hT[i] = {1.0, INFINITY, INFINITY, 0, itr > 0 ? TS_SWEEP : TS_DONE, 0, 0, 0};
+        }
+        HIPCHK(hipMemcpyAsync(bb->dT, hT.data(), sizeof(Track) * count, hipMemcpyHostToDevice, s));
     }
-    HIPCHK(hipEventRecord(g_ev0, s));
-    HIPCHK(launch_solve_batch(precision, bb->dI, bb->dP, bb->dorder, count, o, bb->dR, bb->dticket, blocks, s));
-    HIPCHK(hipEventRecord(g_ev1, s));
+    std::unique_lock<std::mutex> lk(g_time_mu, std::defer_lock);
+    int slot = -1;
+    double sweep_units = 0.0;
+    int rounds = 0;
+    if (timed) {
+        lk.lock();
+        if (!g_ev0) {
+            HIPCHK(hipEventCreate(&g_ev0));
+            HIPCHK(hipEventCreate(&g_ev1));
+        }
+        g_timer.spans.clear();
+        g_timer.on = true;
+        HIPCHK(hipEventRecord(g_ev0, s));
+    }
+    LaunchTimer &tm = g_timer;
+    const bool tmon = timed;
+    auto tbegin = [&](int kind) { return tmon ? tm.begin(kind, s, &slot) : hipSuccess; };
+    auto tend = [&]() { return tmon ? tm.end(slot, s) : hipSuccess; };
+    if (!robust.empty()) {
+        const int n = (int)robust.size();
+        const int blocks = std::max(1, std::min((n + 3) / 4, 4096));
+        HIPCHK(tbegin(2));
+        HIPCHK(launch_solve_batch(precision, bb->dI, bb->dP, bb->dorder, n, o, bb->dR, bb->dticket, blocks, s));
+        HIPCHK(tend());
+    }
+    std::vector<int> resumed, objective;
+    std::vector<char> handed(count, 0);  // handed to the extended-range solver
+    if (any_fast) {
+        bool sweeping[MAXL + 1];
+        for (int l = 0; l <= MAXL; ++l) sweeping[l] = !group[l].empty();
+        std::vector<int64_t> it_before(count, 0);
+        for (;;) {
+            bool any = false;
+            for (int l = 2; l <= MAXL; ++l) {
+                if (!sweeping[l]) continue;
+                any = true;
+                const int n = (int)group[l].size();
+                const int cap = 256 * 8;  // persistent workgroups: a few per CU
+                HIPCHK(tbegin(0));
+                HIPCHK(launch_fast(0, l, precision, bb->dI, bb->dP, bb->dorder + goff[l], n, o, bb->dT, bb->dticket,
+                                   std::min(n, cap), fast_waves(l, gmaxN[l], 0, precision), s));
+                HIPCHK(tend());
+                HIPCHK(tbegin(1));
+                HIPCHK(launch_fast(1, l, precision, bb->dI, bb->dP, bb->dorder + goff[l], n, o, bb->dT, bb->dticket,
+                                   std::min(n, cap), fast_waves(l, gmaxN[l], 1, precision), s));
+                HIPCHK(tend());
+            }
+            if (!any) break;
+            ++rounds;
+            HIPCHK(hipMemcpyAsync(hT.data(), bb->dT, sizeof(Track) * count, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int l = 2; l <= MAXL; ++l) {
+                if (!sweeping[l]) continue;
+                sweeping[l] = false;
+                for (int i : group[l]) {
+                    sweep_units += (double)l * (double)hI[i].N * (double)(hT[i].it - it_before[i]);
+                    it_before[i] = hT[i].it;
+                    if (hT[i].state == TS_SWEEP) sweeping[l] = true;
+                    if (hT[i].state == TS_ROBUST && !handed[i]) {
+                        handed[i] = 1;
+                        resumed.push_back(i);
+                    }
+                }
+            }
+        }
+        for (int l = 2; l <= MAXL; ++l)
+            for (int i : group[l])
+                if (!handed[i] && hT[i].status == ST_OK_HOST && !((flags | hP[i].flags) & F_NO_OBJ))
+                    objective.push_back(i);
+    }
+    if (!resumed.empty()) {
+        // the extended-range solver picks these up where the fast path stopped
+        std::vector<Ptrs> rp(resumed.size());
+        for (size_t k = 0; k < resumed.size(); ++k) {
+            const int i = resumed[k];
+            Ptrs P = hP[i];
+            P.it0 = hT[i].it;
+            P.j0 = hT[i].j0;
+            P.flags |= F_WARM;
+            rp[k] = P;
+            HIPCHK(hipMemcpyAsync(bb->dP + i, &rp[k], sizeof(Ptrs), hipMemcpyHostToDevice, s));
+        }
+        HIPCHK(hipMemcpyAsync(bb->dorder + count, resumed.data(), sizeof(int) * resumed.size(), hipMemcpyHostToDevice,
+                              s));
+        RunOpts ro = o;
+        if (ro.check_every <= 0) ro.check_every = 10;
+        const int n = (int)resumed.size();
+        HIPCHK(tbegin(2));
+        HIPCHK(launch_solve_batch(precision, bb->dI, bb->dP, bb->dorder + count, n, ro, bb->dR, bb->dticket,
+                                  std::max(1, std::min((n + 3) / 4, 4096)), s));
+        HIPCHK(tend());
+        HIPCHK(hipStreamSynchronize(s));  // rp and resumed stay alive until the copies ran
+    }
+    if (!objective.empty()) {
+        HIPCHK(hipMemcpyAsync(bb->dorder + count, objective.data(), sizeof(int) * objective.size(),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(tbegin(2));
+        HIPCHK(launch_objective_batch(bb->dI, bb->dP, bb->dorder + count, (int)objective.size(), bb->dR,
+                                      bb->dticket, s));
+        HIPCHK(tend());
+    }
+    if (timed) HIPCHK(hipEventRecord(g_ev1, s));
     HIPCHK(hipMemcpyAsync(hR, bb->dR, sizeof(Result) * count, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, g_ev0, g_ev1));
-    g_last_kernel_ms = ms;
+    if (timed) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, g_ev0, g_ev1));
+        g_last_kernel_ms = ms;
+        mmot_batch_timing t = {};
+        t.total_ms = ms;
+        for (const auto &sp : tm.spans) {
+            float d = 0.f;
+            HIPCHK(hipEventElapsedTime(&d, tm.pool[sp.e0], tm.pool[sp.e1]));
+            if (sp.kind == 0) {
+                t.sweep_ms += d;
+                ++t.sweep_launches;
+            } else if (sp.kind == 1) {
+                t.check_ms += d;
+            } else {
+                t.other_ms += d;
+            }
+        }
+        t.sweep_units = sweep_units;
+        t.rounds = rounds;
+        g_last_timing = t;
+        tm.on = false;
+    }
+    if (any_fast) {
+        std::vector<char> has_w(count, 0);
+        for (int i : objective) has_w[i] = 1;
+        for (int l = 2; l <= MAXL; ++l)
+            for (int i : group[l]) {
+                if (handed[i]) continue;  // the extended-range solver wrote its own result
+                Result &R = hR[i];
+                const Track &T = hT[i];
+                R.W = has_w[i] ? R.W : 0.0;
+                R.marg_err = T.res;
+                R.iters = T.it;
+                R.status = T.status;
+                R.l = hI[i].l;
+                R.N = hI[i].N;
+                if (R.status == ST_OK_HOST && has_w[i] && !std::isfinite(R.W)) R.status = MMOT_ERR_NUMERIC;
+                if (R.status == ST_OK_HOST && T.checked && o.tol >= 0.0 && !(T.res <= o.tol))
+                    R.status = MMOT_NOT_CONVERGED;
+            }
+    }
     return MMOT_OK;
 }
 
@@ -314,6 +525,15 @@ extern "C" int mmot_last_batch_kernel_ms(double *ms)
     std::lock_guard<std::mutex> lk(g_time_mu);
     if (g_last_kernel_ms < 0) return fail(MMOT_ERR_STATE, "no batch launch yet");
     *ms = g_last_kernel_ms;
+    return MMOT_OK;
+}
+
+extern "C" int mmot_last_batch_timing(mmot_batch_timing *t)
+{
+    if (!t) return fail(MMOT_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    if (g_last_kernel_ms < 0) return fail(MMOT_ERR_STATE, "no batch launch yet");
+    *t = g_last_timing;
     return MMOT_OK;
 }
 
@@ -341,12 +561,12 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
     rc = g_batch.reserve((size_t)count, std::max<size_t>(off, 256));
     if (rc) return rc;
     for (int i = 0; i < count; ++i)
-        hP[i] = {inst[i].log_u, inst[i].log_phi, nullptr, g_batch.scratch + offs[i], 0,
+        hP[i] = {inst[i].log_u, inst[i].log_phi, nullptr, g_batch.scratch + offs[i], 0, 0,
                  (o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0, 0};
-    RunOpts ro = {o->tol, o->itr_max, o->check_every, 0};
-    BatchBuffers bb = {g_batch.dI, g_batch.dP, g_batch.dorder, g_batch.dR, g_batch.dticket};
+    RunOpts ro = {o->tol, o->itr_max, o->check_every, (o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0};
+    BatchBuffers bb = g_batch.bb;
     std::vector<Result> hR(count);
-    rc = batch_launch(hI.data(), hP.data(), count, precision, ro, (hipStream_t)hip_stream, hR.data(), &bb);
+    rc = batch_launch(hI.data(), hP.data(), count, precision, ro, (hipStream_t)hip_stream, hR.data(), &bb, true);
     if (rc) return rc;
     int worst = MMOT_OK;
     for (int i = 0; i < count; ++i) {

@@ -68,9 +68,26 @@ struct Ptrs {
     double *out;          // [N] product output (log J), product mode only
     void *scratch;        // per-chunk scan checkpoints
     int64_t itr_cap;      // sweeps allowed for this instance in this launch (0: RunOpts.itr_max)
+    int64_t it0;          // sweeps already done (resumed solves)
     int32_t flags;        // OR-ed with RunOpts.flags
-    int32_t pad;
+    int32_t j0;           // resumed solves: sweep it0 goes on at marginal j0 (l: sweep done, check first)
 };
+
+// Progress of one fast-path solve across the sweep and check launches.
+struct Track {
+    double f;         // the estimate asks for a check once it falls below tol * f
+    double est;       // marginal-error estimate of the last sweep
+    double res;       // last FP64 residual (+inf before the first)
+    int64_t it;       // sweeps done
+    int32_t state;    // TS_*
+    int32_t status;   // final status once state is TS_DONE
+    int32_t j0;       // TS_ROBUST: marginal at which the extended-range solver resumes
+    int32_t checked;  // a residual has been taken
+};
+constexpr int32_t TS_SWEEP = 0;   // the sweep kernel goes on with it
+constexpr int32_t TS_CHECK = 1;   // a residual check is due
+constexpr int32_t TS_ROBUST = 2;  // the extended-range solver takes it over
+constexpr int32_t TS_DONE = 3;
 
 // Stopping rule of one launch.
 struct RunOpts {
@@ -94,6 +111,7 @@ struct Result {
 constexpr int32_t F_WARM = 1;        // keep the given potentials
 constexpr int32_t F_NO_CHECK = 2;    // no residual check at all
 constexpr int32_t F_NO_OBJ = 4;      // skip the objective
+constexpr int32_t F_NO_FAST = 8;     // host only: every instance on the extended-range solver
 
 // Lane width V per (l, pass kind) -- trades registers against scan overhead.
 // kind 0: FP32 update, 1: FP64 update and product, 2: FP64 objective
@@ -104,6 +122,27 @@ constexpr int vsel(int l, int kind)
          : kind == 1 ? (l <= 2 ? 8 : l == 3 ? 4 : l == 4 ? 2 : 1)
          : kind == 2 ? (l <= 2 ? 2 : 1)
                      : (l <= 2 ? 4 : l == 3 ? 2 : 1);
+}
+
+// Register-resident fast path (fast.hpp): positions per thread V and threads
+// per workgroup by l and precision (1: FP32 sweeps, 0: FP64); an instance fits if
+// N <= fast_threads * fast_v.
+constexpr int FAST_MAXL = 4;            // largest l the fast path is built for
+constexpr bool FAST_PATH_ENABLED = false;  // host routing to the fast path (see fast_eligible)
+constexpr int fast_v(int l, int precision)
+{
+    return precision == 1 ? (l <= 4 ? 4 : l == 5 ? 2 : 1) : (l <= 4 ? 2 : 1);
+}
+constexpr int fast_threads(int l, int precision) { return precision == 1 || l >= 6 ? 256 : 512; }
+constexpr long fast_capacity(int l, int precision) { return (long)fast_threads(l, precision) * fast_v(l, precision); }
+
+// Block floating point holds while the values one thread keeps span at most
+// this many bits: rows of l - 1 marginals (row_spread bits each), v positions
+// of discount (decay_bits each), and the product of a forward and a backward
+// state in the combine must stay normal (FP32: 2^-126, FP64: 2^-1022).
+constexpr bool bf_fits_range(int precision, int l, int v, int row_spread, int decay_bits)
+{
+    return 2 * ((l - 1) * row_spread + v * decay_bits + l + 4) <= (precision == 1 ? 120 : 1000);
 }
 
 // Bytes of one scan element of each kind (for checkpoint storage).

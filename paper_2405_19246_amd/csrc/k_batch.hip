@@ -1,9 +1,33 @@
 // The persistent mixed-l batch kernels and the launch dispatchers.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace mmot {
 
 __global__ void k_fill_int(int *p, int v) { *p = v; }
+
+__global__ __launch_bounds__(256) void k_objective_batch(const Inst *I, const Ptrs *P, const int *list, int count,
+                                                         Result *R, int *ticket)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(ticket, 1);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        if (t >= count) break;
+        const int idx = __builtin_amdgcn_readfirstlane(list[t]);
+        switch (I[idx].l) {
+            case 2: objective_one<2>(&I[idx], P[idx], &R[idx], lane); break;
+            case 3: objective_one<3>(&I[idx], P[idx], &R[idx], lane); break;
+            case 4: objective_one<4>(&I[idx], P[idx], &R[idx], lane); break;
+            case 5: objective_one<5>(&I[idx], P[idx], &R[idx], lane); break;
+            case 6: objective_one<6>(&I[idx], P[idx], &R[idx], lane); break;
+            default: break;
+        }
+    }
+}
+
 
 hipError_t launch_solve_batch(int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,
                               const RunOpts &o, Result *dR, int *dticket, int blocks, hipStream_t s)
@@ -27,6 +51,22 @@ hipError_t launch_solve_batch(int precision, const Inst *dI, const Ptrs *dP, con
         case 6: return fn##6(__VA_ARGS__);          \
         default: return hipErrorInvalidValue;       \
     }
+
+hipError_t launch_fast(int kind, int l, int precision, const Inst *dI, const Ptrs *dP, const int *dlist, int count,
+                       const RunOpts &o, Track *dT, int *dticket, int blocks, int waves, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, dticket, 0);
+    MMOT_DISPATCH(launch_fast_l, l, kind, precision, dI, dP, dlist, count, o, dT, dticket, blocks, waves, s)
+}
+
+hipError_t launch_objective_batch(const Inst *dI, const Ptrs *dP, const int *dlist, int count, Result *dR,
+                                  int *dticket, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, dticket, 0);
+    const int blocks = std::max(1, std::min((count + 3) / 4, 4096));
+    hipLaunchKernelGGL(k_objective_batch, dim3(blocks), dim3(256), 0, s, dI, dP, dlist, count, dR, dticket);
+    return hipGetLastError();
+}
 
 hipError_t launch_pass(int l, int precision, int mode, const Inst *dI, const Ptrs &P, int j, double *dres,
                        hipStream_t s)

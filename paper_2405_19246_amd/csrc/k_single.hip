@@ -43,6 +43,26 @@ static hipError_t launch_single_t(int precision, const Inst *dI, const Ptrs &P, 
     return hipGetLastError();
 }
 
+template <int L>
+static hipError_t launch_fast_t(int kind, int precision, const Inst *dI, const Ptrs *dP, const int *dlist,
+                                int count, const RunOpts &o, Track *dT, int *dticket, int blocks, int waves,
+                                hipStream_t s)
+{
+    if constexpr (L > FAST_MAXL) {
+        return hipErrorInvalidValue;
+    } else {
+    const dim3 g(blocks), b(WAVE * waves);
+    if (kind == 1)
+        hipLaunchKernelGGL((k_fast_check<L, fast_v(L, 0)>), g, b, 0, s, dI, dP, dlist, count, o, dT, dticket);
+    else if (precision == 1)
+        hipLaunchKernelGGL((k_fast_sweep<L, fast_v(L, 1), float>), g, b, 0, s, dI, dP, dlist, count, o, dT, dticket);
+    else
+        hipLaunchKernelGGL((k_fast_sweep<L, fast_v(L, 0), double>), g, b, 0, s, dI, dP, dlist, count, o, dT,
+                           dticket);
+    return hipGetLastError();
+    }
+}
+
 #define MMOT_CAT2(a, b) a##b
 #define MMOT_CAT(a, b) MMOT_CAT2(a, b)
 
@@ -56,6 +76,13 @@ hipError_t MMOT_CAT(launch_single_l, MMOT_L)(int precision, const Inst *dI, cons
                                               Result *dR, hipStream_t s)
 {
     return launch_single_t<MMOT_L>(precision, dI, P, o, dR, s);
+}
+
+hipError_t MMOT_CAT(launch_fast_l, MMOT_L)(int kind, int precision, const Inst *dI, const Ptrs *dP,
+                                            const int *dlist, int count, const RunOpts &o, Track *dT, int *dticket,
+                                            int blocks, int waves, hipStream_t s)
+{
+    return launch_fast_t<MMOT_L>(kind, precision, dI, dP, dlist, count, o, dT, dticket, blocks, waves, s);
 }
 
 }  // namespace mmot

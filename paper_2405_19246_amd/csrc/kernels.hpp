@@ -10,23 +10,11 @@
 #pragma once
 #include <type_traits>
 
+#include "fast.hpp"
 #include "launch.hpp"
 #include "scan.hpp"
 
 namespace mmot {
-
-static constexpr int ST_OK = 0;
-static constexpr int ST_NUMERIC = -3;
-static constexpr int ST_NOT_CONVERGED = -4;
-
-template <int L, typename M>
-__device__ __forceinline__ const Disc<M> *upd_disc(const Inst *I)
-{
-    if constexpr (std::is_same<M, float>::value)
-        return &I->d32;
-    else
-        return &I->d64;
-}
 
 // Whole solve of one instance on one wavefront.
 template <int L, typename M>
@@ -42,23 +30,34 @@ __device__ void solve_one(const Inst *__restrict__ I, const Ptrs P, const RunOpt
     const int flags = o.flags | P.flags;
     const long itr_max = P.itr_cap > 0 ? P.itr_cap : o.itr_max;
 
-    if (!(flags & F_WARM)) {
+    if (!(flags & F_WARM) && P.it0 == 0) {
         // phi = 1/N (Alg. 1 initialisation)
         const double a0 = -log((double)N);
         for (long p = lane; p < (long)L * N; p += WAVE) a[p] = a0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    long it = 0;
-    double res = INFINITY;
+    // a resumed solve finishes sweep it0 from marginal j0 first (j0 = l: only its check)
+    long it = P.it0;
+    int jr = P.j0;
+    double res = INFINITY, f = 1.0;
     int status = ST_OK;
     bool checked = false;
-    while (it < itr_max) {
-        ++it;
-        for (int j = 0; j < L; ++j)
-            marginal_pass<L, VU, XF<M>, P_UPDATE>(I, upd_disc<L, M>(I), j, a, lu, nullptr, P.scratch, lane);
+    while (it < itr_max || jr > 0) {
+        const bool resumed = jr > 0;
+        if (!resumed) ++it;
+        // est: marginal errors the updates of this sweep removed (j < l-1)
+        double est = 0.0;
+        for (int j = jr; j < L; ++j) {
+            const double e =
+                marginal_pass<L, VU, XF<M>, P_UPDATE>(I, upd_disc<L, M>(I), j, a, lu, nullptr, P.scratch, lane);
+            if (j < L - 1) est += e;
+        }
+        jr = 0;
+        const bool trig = !resumed && o.tol >= 0.0 && est <= o.tol * f;
         const bool chk = !(flags & F_NO_CHECK) &&
-                         ((o.check_every > 0 && it % o.check_every == 0) || it == itr_max);
+                         ((resumed && P.j0 == L) || (o.check_every > 0 && it % o.check_every == 0) ||
+                          it >= itr_max || trig);
         if (chk) {
             checked = true;
             res = 0.0;
@@ -69,6 +68,7 @@ __device__ void solve_one(const Inst *__restrict__ I, const Ptrs P, const RunOpt
                 break;
             }
             if (res <= o.tol) break;
+            if (trig) f *= 0.5;
         }
     }
     double W = 0.0;
@@ -152,6 +152,56 @@ __global__ __launch_bounds__(64) void k_check_all(const Inst *I, Ptrs P, double 
                                                                   threadIdx.x);
         if (threadIdx.x == 0) err[j] = r;
     }
+}
+
+// Fast path, sweeps: each workgroup takes the next instance of the list (all
+// have l = L and N <= blockDim.x * V) and, if its state is TS_SWEEP, runs
+// fast_sweeps on it.
+template <int L, int V, typename M>
+__global__ __launch_bounds__(fast_threads(L, sizeof(M) == 4 ? 1 : 0)) void k_fast_sweep(
+    const Inst *I, const Ptrs *P, const int *list, int count, RunOpts o, Track *Tr, int *ticket)
+{
+    __shared__ FastShared<L, V, M> sh;
+    __shared__ int tk;
+    for (;;) {
+        if (threadIdx.x == 0) tk = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int t = tk;
+        __syncthreads();
+        if (t >= count) break;
+        const int idx = list[t];
+        if (Tr[idx].state == TS_SWEEP) fast_sweeps<L, V, M>(&I[idx], P[idx], o, &Tr[idx], sh);
+        __syncthreads();
+    }
+}
+
+// Fast path, FP64 residual checks of the instances in state TS_CHECK.
+template <int L, int V>
+__global__ __launch_bounds__(fast_threads(L, 0)) void k_fast_check(const Inst *I, const Ptrs *P, const int *list,
+                                                                int count, RunOpts o, Track *Tr, int *ticket)
+{
+    __shared__ FastShared<L, V, double> sh;
+    __shared__ int tk;
+    for (;;) {
+        if (threadIdx.x == 0) tk = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int t = tk;
+        __syncthreads();
+        if (t >= count) break;
+        const int idx = list[t];
+        if (Tr[idx].state == TS_CHECK) fast_check<L, V>(&I[idx], P[idx], o, &Tr[idx], sh);
+        __syncthreads();
+    }
+}
+
+// FP64 objective (Sec. 2 Eq. mmot distance) of each listed instance, one
+// wavefront per instance; writes Result.W only.
+template <int L>
+__device__ void objective_one(const Inst *I, const Ptrs P, Result *R, int lane)
+{
+    constexpr int VO = vsel(L, 2);
+    const double W = marginal_pass<L, VO, DXF, P_OBJECTIVE>(I, &I->dob, L - 1, P.a, P.log_u, nullptr, P.scratch, lane);
+    if (lane == 0) R->W = W;
 }
 
 }  // namespace mmot

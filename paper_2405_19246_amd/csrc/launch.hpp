@@ -21,13 +21,26 @@ hipError_t launch_solve_single(int l, int precision, const Inst *dI, const Ptrs 
     hipError_t launch_pass_l##l(int precision, int mode, const Inst *dI, const Ptrs &P, int j, double *dres, \
                                 hipStream_t s);                                                        \
     hipError_t launch_single_l##l(int precision, const Inst *dI, const Ptrs &P, const RunOpts &o, Result *dR, \
-                                  hipStream_t s);
+                                  hipStream_t s);                                                        \
+    hipError_t launch_fast_l##l(int kind, int precision, const Inst *dI, const Ptrs *dP, const int *dlist,    \
+                                int count, const RunOpts &o, Track *dT, int *dticket, int blocks, int waves,   \
+                                hipStream_t s);
 MMOT_DECL_L(2)
 MMOT_DECL_L(3)
 MMOT_DECL_L(4)
 MMOT_DECL_L(5)
 MMOT_DECL_L(6)
 #undef MMOT_DECL_L
+
+// Fast path over a list of instances that all have l and N <= waves * 64 * V:
+// kind 0 runs the sweeps (V = fast_v(l, precision)), kind 1 the FP64 residual
+// checks (V = fast_v(l, 0)).  Resets *dticket first.
+hipError_t launch_fast(int kind, int l, int precision, const Inst *dI, const Ptrs *dP, const int *dlist, int count,
+                       const RunOpts &o, Track *dT, int *dticket, int blocks, int waves, hipStream_t s);
+
+// FP64 objective of each listed instance (Result.W only).  Resets *dticket first.
+hipError_t launch_objective_batch(const Inst *dI, const Ptrs *dP, const int *dlist, int count, Result *dR,
+                                  int *dticket, hipStream_t s);
 
 hipError_t launch_solve_batch(int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,
                               const RunOpts &o, Result *dR, int *dticket, int blocks, hipStream_t s);

@@ -28,6 +28,7 @@
 // carry-in from the previous chunk added in closed form g^{t+1} c.  Chunks are
 // walked in order; the backward direction mirrors lanes and positions.
 #pragma once
+#include <type_traits>
 #include "xf.hpp"
 
 namespace mmot {
@@ -116,6 +117,21 @@ __device__ __forceinline__ void level_scan(const XF<typename ET<E>::MT> (&phi)[L
     }
 }
 
+// Result.status values set on the device.
+static constexpr int ST_OK = 0;
+static constexpr int ST_NUMERIC = -3;
+static constexpr int ST_NOT_CONVERGED = -4;
+
+// Discount table of the update pass in mantissa type M.
+template <int L, typename M>
+__device__ __forceinline__ const Disc<M> *upd_disc(const Inst *I)
+{
+    if constexpr (std::is_same<M, float>::value)
+        return &I->d32;
+    else
+        return &I->d64;
+}
+
 enum PassMode { P_PRODUCT = 0, P_UPDATE = 1, P_CHECK = 2, P_OBJECTIVE = 3 };
 
 template <typename E>
@@ -146,7 +162,9 @@ __device__ __forceinline__ XF<double> wave_sum_xf(XF<double> x)
 
 // One marginal pass over an instance on one wavefront.
 //   P_PRODUCT:   out[y] = log J_j(y)
-//   P_UPDATE:    a_j(y) = log u_j(y) - log J_j(y)           (Gauss-Seidel step)
+//   P_UPDATE:    a_j(y) = log u_j(y) - log J_j(y)           (Gauss-Seidel step);
+//                returns sum_y u_j(y) |exp(a_j,old(y) - a_j(y)) - 1|, the
+//                marginal error before the step (FP64)
 //   P_CHECK:     returns sum_y |exp(a_j(y) + log J_j(y)) - u_j(y)|  (FP64)
 //   P_OBJECTIVE: returns h sum_y phi_j(y) ((C o K) x_{q != j} phi_q)(y) / h ... = W_eps
 // a: [l][N] potentials; scratch: checkpoint space for ceil(N / 64V) (D - 1) elements.
@@ -245,7 +263,12 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
                     if constexpr (MODE == P_PRODUCT) {
                         out[p] = lj;
                     } else if constexpr (MODE == P_UPDATE) {
-                        a[(long)j * N + p] = log_u[(long)j * N + p] - lj;
+                        // marginal error this update removes: u |exp(a_old - a_new) - 1|
+                        const double lu = log_u[(long)j * N + p];
+                        const double ao = a[(long)j * N + p];
+                        const double an = lu > -INFINITY ? lu - lj : -INFINITY;
+                        if (lu > -INFINITY) acc += exp(lu) * fabs(expm1(ao - an));
+                        a[(long)j * N + p] = an;
                     } else {
                         const double lu = log_u[(long)j * N + p];
                         acc += fabs(exp(a[(long)j * N + p] + lj) - exp(lu));
@@ -257,6 +280,7 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
     if constexpr (MODE == P_UPDATE) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        return wave_sum(acc);
     }
     if constexpr (MODE == P_CHECK) return wave_sum(acc);
     if constexpr (MODE == P_OBJECTIVE) return I->h * xto_double(wave_sum_xf(accx));

@@ -136,6 +136,7 @@ struct mmot_server {
 
     void loop();
     int finish(std::vector<Slot> &slots, const std::vector<int> &fin, const std::vector<Result> &hR);
+    int path_flag() const { return (cfg.opts.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0; }
 };
 
 int mmot_server::finish(std::vector<Slot> &slots, const std::vector<int> &fin, const std::vector<Result> &hR)
@@ -151,7 +152,7 @@ int mmot_server::finish(std::vector<Slot> &slots, const std::vector<int> &fin, c
         hP[k].itr_cap = 0;
         hP[k].flags = F_WARM;
     }
-    RunOpts ro = {cfg.opts.tol, 0, cfg.opts.check_every, 0};
+    RunOpts ro = {cfg.opts.tol, 0, cfg.opts.check_every, path_flag()};
     int rc = batch_launch(hI.data(), hP.data(), n, cfg.precision, ro, s, hW.data(), &bb);
     if (rc) return rc;
     const double t = now_s();
@@ -220,7 +221,7 @@ void mmot_server::loop()
             const size_t rows = Arena::round_up(sizeof(double) * (size_t)r.l * (size_t)r.N);
             char *p = base + sl.off;
             sl.I = make_inst(r.l, r.N, r.h, r.eps);
-            sl.P = {(const double *)p, (double *)(p + rows), nullptr, p + 2 * rows, 0, 0, 0};
+            sl.P = {(const double *)p, (double *)(p + rows), nullptr, p + 2 * rows, 0, 0, 0, 0};
             if (hipMemcpyAsync(p, r.log_u.data(), sizeof(double) * r.log_u.size(), hipMemcpyHostToDevice, s) !=
                 hipSuccess) {
                 error = MMOT_ERR_HIP;
@@ -240,7 +241,7 @@ void mmot_server::loop()
             hP[i].itr_cap = std::max<int64_t>(1, std::min<int64_t>(cfg.block_sweeps, left));
             hP[i].flags = slots[i].started ? F_WARM : 0;
         }
-        RunOpts ro = {cfg.opts.tol, cfg.block_sweeps, cfg.opts.check_every, F_NO_OBJ};
+        RunOpts ro = {cfg.opts.tol, cfg.block_sweeps, cfg.opts.check_every, F_NO_OBJ | path_flag()};
         int rc = batch_launch(hI.data(), hP.data(), n, cfg.precision, ro, s, hR.data(), &bb);
         if (rc) {
             std::lock_guard<std::mutex> lk(mu);
@@ -291,19 +292,11 @@ int mmot_serve_start(const mmot_serve_cfg *cfg, mmot_server_t **out)
     hipError_t e = hipStreamCreate(&srv->s);
     if (e == hipSuccess) e = hipMalloc((void **)&srv->base, cfg->hbm_budget_bytes);
     const size_t c = (size_t)cfg->max_slots;
-    if (e == hipSuccess) e = hipMalloc((void **)&srv->bb.dI, sizeof(Inst) * c);
-    if (e == hipSuccess) e = hipMalloc((void **)&srv->bb.dP, sizeof(Ptrs) * c);
-    if (e == hipSuccess) e = hipMalloc((void **)&srv->bb.dorder, sizeof(int) * c);
-    if (e == hipSuccess) e = hipMalloc((void **)&srv->bb.dR, sizeof(Result) * c);
-    if (e == hipSuccess) e = hipMalloc((void **)&srv->bb.dticket, sizeof(int));
+    if (e == hipSuccess) e = batch_buffers_alloc(&srv->bb, c);
     if (e != hipSuccess) {
         mmot_server *p = srv.release();
         if (p->base) (void)hipFree(p->base);
-        if (p->bb.dI) (void)hipFree(p->bb.dI);
-        if (p->bb.dP) (void)hipFree(p->bb.dP);
-        if (p->bb.dorder) (void)hipFree(p->bb.dorder);
-        if (p->bb.dR) (void)hipFree(p->bb.dR);
-        if (p->bb.dticket) (void)hipFree(p->bb.dticket);
+        batch_buffers_free(&p->bb);
         if (p->s) (void)hipStreamDestroy(p->s);
         delete p;
         return fail(e == hipErrorOutOfMemory ? MMOT_ERR_NOMEM : MMOT_ERR_HIP,
@@ -382,11 +375,7 @@ int mmot_serve_stop(mmot_server_t *srv)
     const int err = srv->error;
     const std::string msg = srv->error_msg;
     (void)hipFree(srv->base);
-    (void)hipFree(srv->bb.dI);
-    (void)hipFree(srv->bb.dP);
-    (void)hipFree(srv->bb.dorder);
-    (void)hipFree(srv->bb.dR);
-    (void)hipFree(srv->bb.dticket);
+    batch_buffers_free(&srv->bb);
     (void)hipStreamDestroy(srv->s);
     delete srv;
     return err ? fail(err, msg) : MMOT_OK;

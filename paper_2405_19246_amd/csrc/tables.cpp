@@ -77,6 +77,26 @@ size_t scratch_bytes(int l, int64_t N, int precision)
     return (best + 255) & ~(size_t)255;
 }
 
+bool fast_eligible(const Inst &I, int precision)
+{
+    // Switched off: the first GPU run of the register-resident path did not
+    // finish (no fault reported); its cause has not been found, so no solve is
+    // routed there until it is.
+    if (!FAST_PATH_ENABLED) return false;
+    const int l = I.l;
+    if (l < 2 || l > FAST_MAXL) return false;
+    if (I.N > std::min(fast_capacity(l, precision), fast_capacity(l, 0))) return false;
+    int dec = 0;
+    for (int k = 0; k < l; ++k) dec = std::max(dec, 1 - host_xg<double>(-(double)(k * (l - k)) * I.hoe).e);
+    return bf_fits_range(precision, l, fast_v(l, precision), 0, dec) && bf_fits_range(0, l, fast_v(l, 0), 0, dec);
+}
+
+int fast_waves(int l, int64_t N, int kind, int precision)
+{
+    const int p = kind == 1 ? 0 : precision;
+    const int64_t per = (int64_t)WAVE * fast_v(l, p);
+    return (int)std::max<int64_t>(1, (N + per - 1) / per);
+}
 
 }  // namespace rt
 }  // namespace mmot

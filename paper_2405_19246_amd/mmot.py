@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmmot.so")
 OK, ERR_INVALID, ERR_NOMEM, ERR_NUMERIC, NOT_CONVERGED, ERR_UNSUPPORTED, ERR_HIP, ERR_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
 FLAG_WARM_START = 1
+FLAG_NO_FAST = 2
 MAX_L = 8
 
 _c_d, _c_i32, _c_i64, _c_p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
@@ -62,12 +63,17 @@ class ServeStats(ctypes.Structure):
                 ("p99_latency", _c_d), ("units_per_second", _c_d)]
 
 
+class BatchTiming(ctypes.Structure):
+    _fields_ = [("total_ms", _c_d), ("sweep_ms", _c_d), ("check_ms", _c_d), ("other_ms", _c_d),
+                ("sweep_units", _c_d), ("sweep_launches", _c_i32), ("rounds", _c_i32)]
+
+
 REQUEST_FN = ctypes.CFUNCTYPE(ctypes.c_int, _c_p, _c_i64, ctypes.POINTER(Request), ctypes.POINTER(_c_d))
 
 EXPORTS = ["mmot_plan", "mmot_plan_footprint", "mmot_plan_destroy", "mmot_marginal_product", "mmot_sinkhorn_iter",
            "mmot_solve", "mmot_objective", "mmot_marginal_errors", "mmot_solve_batch", "mmot_serve_start",
            "mmot_serve_submit", "mmot_serve_poll", "mmot_serve_stop", "mmot_serve", "mmot_last_batch_kernel_ms",
-           "mmot_last_error"]
+           "mmot_last_batch_timing", "mmot_last_error"]
 
 
 class MmotError(RuntimeError):
@@ -103,6 +109,7 @@ def lib() -> ctypes.CDLL:
         L.mmot_serve_stop.argtypes = [_c_p]
         L.mmot_serve.argtypes = [PP(ServeCfg), REQUEST_FN, _c_p, PP(ServeStats), PP(RequestRecord), _c_i64]
         L.mmot_last_batch_kernel_ms.argtypes = [PP(_c_d)]
+        L.mmot_last_batch_timing.argtypes = [PP(BatchTiming)]
         L.mmot_last_error.argtypes = []
         L.mmot_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
@@ -127,6 +134,10 @@ def _stream_handle(stream) -> int:
     return int(s.cuda_stream)
 
 
+def _flags(warm_start: bool, fast: bool) -> int:
+    return (FLAG_WARM_START if warm_start else 0) | (0 if fast else FLAG_NO_FAST)
+
+
 def _dev_f64(t, shape, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -142,11 +153,12 @@ class Plan:
     """Execution plan for one problem shape (mmot_plan)."""
 
     def __init__(self, l: int, N: int, h: float, eps: float, precision: int = FP64, tol: float = 1e-8,
-                 itr_max: int = 1000, check_every: int = 10, warm_start: bool = False, stream=None):
+                 itr_max: int = 1000, check_every: int = 10, warm_start: bool = False, stream=None,
+                 fast: bool = True):
         self.l, self.N, self.h, self.eps, self.precision = int(l), int(N), float(h), float(eps), int(precision)
         self.stream = stream
         p = Problem(self.l, self.N, self.h, self.eps, self.precision)
-        o = Opts(float(tol), int(itr_max), int(check_every), FLAG_WARM_START if warm_start else 0)
+        o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast))
         h_ = _c_p()
         _check(lib().mmot_plan(ctypes.byref(p), ctypes.byref(o), _c_p(_stream_handle(stream)), ctypes.byref(h_)))
         self._h = h_
@@ -209,22 +221,31 @@ class Plan:
 
 
 def last_batch_kernel_ms() -> float:
-    """Device time of the last persistent batch kernel (HIP events on its stream)."""
+    """Device time of the last solve_batch, first kernel to last (HIP events on its stream)."""
     ms = _c_d()
     _check(lib().mmot_last_batch_kernel_ms(ctypes.byref(ms)))
     return ms.value
 
 
+def last_batch_timing() -> dict:
+    """Per-launch breakdown of the last solve_batch (mmot_last_batch_timing)."""
+    t = BatchTiming()
+    _check(lib().mmot_last_batch_timing(ctypes.byref(t)))
+    return {k: getattr(t, k) for k, _ in BatchTiming._fields_}
+
+
 def solve_batch(instances: Sequence[dict], precision: int = FP32, tol: float = 1e-6, itr_max: int = 100000,
-                check_every: int = 10, warm_start: bool = False, stream=None) -> list:
-    """mmot_solve_batch: instances are dicts with l, N, h, eps, log_u, log_phi (device tensors)."""
+                check_every: int = 10, warm_start: bool = False, stream=None, fast: bool = True) -> list:
+    """mmot_solve_batch: instances are dicts with l, N, h, eps, log_u, log_phi (device tensors).
+
+    fast=False sets MMOT_FLAG_NO_FAST (every solve on the extended-range solver)."""
     n = len(instances)
     arr = (Instance * max(n, 1))()
     for i, d in enumerate(instances):
         pu = _dev_f64(d["log_u"], (d["l"], d["N"]), "log_u")
         pa = _dev_f64(d["log_phi"], (d["l"], d["N"]), "log_phi")
         arr[i] = Instance(int(d["l"]), int(d["N"]), float(d["h"]), float(d["eps"]), pu, pa)
-    o = Opts(float(tol), int(itr_max), int(check_every), FLAG_WARM_START if warm_start else 0)
+    o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast))
     res = (Result * max(n, 1))()
     _check(lib().mmot_solve_batch(arr, n, int(precision), ctypes.byref(o), _c_p(_stream_handle(stream)), res),
            allow=(OK, NOT_CONVERGED))
@@ -235,9 +256,9 @@ class Server:
     """Non-blocking continuous-batching server (mmot_serve_start/submit/poll/stop)."""
 
     def __init__(self, precision: int = FP32, tol: float = 1e-6, itr_max: int = 100000, check_every: int = 10,
-                 max_slots: int = 1024, block_sweeps: int = 50, hbm_budget_bytes: int = 8 << 30):
-        self.cfg = ServeCfg(int(precision), Opts(float(tol), int(itr_max), int(check_every), 0), int(max_slots),
-                            int(block_sweeps), int(hbm_budget_bytes))
+                 max_slots: int = 1024, block_sweeps: int = 50, hbm_budget_bytes: int = 8 << 30, fast: bool = True):
+        self.cfg = ServeCfg(int(precision), Opts(float(tol), int(itr_max), int(check_every), _flags(False, fast)),
+                            int(max_slots), int(block_sweeps), int(hbm_budget_bytes))
         h = _c_p()
         _check(lib().mmot_serve_start(ctypes.byref(self.cfg), ctypes.byref(h)))
         self._h = h
@@ -283,7 +304,7 @@ class Server:
 
 def serve(requests: Callable[[int], tuple | None], precision: int = FP32, tol: float = 1e-6, itr_max: int = 100000,
           check_every: int = 10, max_slots: int = 1024, block_sweeps: int = 50, hbm_budget_bytes: int = 8 << 30,
-          max_records: int = 0):
+          max_records: int = 0, fast: bool = True):
     """Blocking mmot_serve.  requests(i) returns (u [l, N] array, h, eps, t_arrive) or None when done."""
     keep = {}
 
@@ -300,8 +321,8 @@ def serve(requests: Callable[[int], tuple | None], precision: int = FP32, tol: f
         return 0
 
     cb = REQUEST_FN(_cb)
-    cfg = ServeCfg(int(precision), Opts(float(tol), int(itr_max), int(check_every), 0), int(max_slots),
-                   int(block_sweeps), int(hbm_budget_bytes))
+    cfg = ServeCfg(int(precision), Opts(float(tol), int(itr_max), int(check_every), _flags(False, fast)),
+                   int(max_slots), int(block_sweeps), int(hbm_budget_bytes))
     stats = ServeStats()
     recs = (RequestRecord * max(max_records, 1))()
     _check(lib().mmot_serve(ctypes.byref(cfg), cb, None, ctypes.byref(stats), recs if max_records else None,

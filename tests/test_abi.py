@@ -39,6 +39,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(mmot.Opts) == 24
     assert ctypes.sizeof(mmot.Result) == 40
     assert ctypes.sizeof(mmot.Instance) == 48
+    assert ctypes.sizeof(mmot.BatchTiming) == 48
 
 
 @pytest.mark.parametrize("l,N,h,eps,code", [

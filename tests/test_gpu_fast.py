@@ -1,0 +1,143 @@
+"""Register-resident solver (one workgroup per instance) against the oracle and
+against the extended-range solver (MMOT_FLAG_NO_FAST)."""
+import numpy as np
+import pytest
+
+from gpu_util import potentials_err, say, to_dev
+from oracle import fastcheck
+from paper_2405_19246_amd import inputs
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="register-resident path switched off: its first GPU run did not finish "
+                                      "and the cause is not found yet")]
+
+FP64_TOL = 1e-12
+
+
+def _mmot():
+    from paper_2405_19246_amd import mmot
+    return mmot
+
+
+def _inst(l, N, eps, seed, K=3):
+    u = inputs.marginals(l, N, K=K, master_seed=seed, instance=l * 100000 + N)
+    return dict(l=l, N=N, h=inputs.grid_step(max(N, 2)), eps=eps, u=u)
+
+
+def _dev(insts):
+    for d in insts:
+        d["log_u"] = to_dev(np.log(d["u"]))
+        d["log_phi"] = to_dev(np.zeros((d["l"], d["N"])))
+    return insts
+
+
+# N = 1 .. capacity (1024 for l <= 4) and one past it, several tiles and ragged tails
+SHAPES = [(2, 1), (2, 129), (3, 64), (3, 65), (3, 1000), (4, 63), (4, 300), (4, 1000), (4, 1024), (4, 1025),
+          (2, 1024), (3, 511)]
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.01])
+def test_fast_fp64_fixed_sweeps_match_oracle(eps):
+    mmot = _mmot()
+    insts = _dev([_inst(l, N, eps, seed=21) for (l, N) in SHAPES])
+    say("fast fp64 %d shapes eps=%g, 25 sweeps" % (len(insts), eps))
+    res = mmot.solve_batch(insts, precision=mmot.FP64, tol=-1.0, itr_max=25, check_every=0)
+    for d, r in zip(insts, res):
+        ref = fastcheck.sinkhorn(d["u"], d["h"], d["eps"], itmax=25, check_every=25)
+        got = d["log_phi"].cpu().numpy()
+        assert r["iters"] == 25 and r["status"] == 0, (d["l"], d["N"], r)
+        assert potentials_err(got, ref["log_phi"]) < FP64_TOL, (d["l"], d["N"], potentials_err(got, ref["log_phi"]))
+        assert abs(r["W"] - ref["W"]) <= FP64_TOL * abs(ref["W"]) + 1e-300, (d["l"], d["N"])
+        assert abs(r["marg_err"] - ref["res"]) <= 1e-9 * ref["res"] + 1e-15, (d["l"], d["N"])
+
+
+def test_fast_fp64_equals_extended_range_solver():
+    mmot = _mmot()
+    a = _dev([_inst(l, N, 0.02, seed=22) for (l, N) in SHAPES])
+    b = _dev([_inst(l, N, 0.02, seed=22) for (l, N) in SHAPES])
+    say("fast vs extended-range fp64, 40 sweeps")
+    ra = mmot.solve_batch(a, precision=mmot.FP64, tol=-1.0, itr_max=40, check_every=0)
+    rb = mmot.solve_batch(b, precision=mmot.FP64, tol=-1.0, itr_max=40, check_every=0, fast=False)
+    for da, db, x, y in zip(a, b, ra, rb):
+        assert x["iters"] == y["iters"] == 40
+        assert potentials_err(da["log_phi"].cpu().numpy(), db["log_phi"].cpu().numpy()) < FP64_TOL
+        assert abs(x["W"] - y["W"]) <= FP64_TOL * abs(y["W"])
+
+
+def test_fast_fp32_one_sweep_from_oracle_iterates():
+    # FP32 sweeps: from the oracle's iterate after k sweeps, one device sweep
+    # lands within the FP32 product error of the oracle's next iterate.
+    mmot = _mmot()
+    u, h, eps = inputs.workload("l4_n1000_eps0.01", instance=3)
+    plan = mmot.Plan(4, 1000, h, eps, precision=mmot.FP32, tol=-1.0, itr_max=1, check_every=0)
+    log_u = to_dev(np.log(u))
+    a = np.full((4, 1000), -np.log(1000.0))
+    done = 0
+    worst = 0.0
+    for k in (0, 5, 50, 400):
+        if k > done:
+            a = fastcheck.sinkhorn(u, h, eps, itmax=k - done, check_every=10**9, log_phi0=a)["log_phi"]
+            done = k
+        say("fast fp32 one sweep from oracle iterate %d" % k)
+        t = to_dev(a)
+        plan.sinkhorn_iter(log_u, t, 1, want_err=False)
+        ref = fastcheck.sinkhorn(u, h, eps, itmax=1, check_every=10**9, log_phi0=a)["log_phi"]
+        e = potentials_err(t.cpu().numpy(), ref)
+        worst = max(worst, e)
+        assert e < 2e-5, (k, e)
+    print("fast fp32 one sweep: worst potentials error %.3e" % worst)
+
+
+def test_fast_fp32_solves_certified():
+    mmot = _mmot()
+    insts = _dev([_inst(l, N, eps, seed=23) for (l, N) in SHAPES for eps in (0.1, 0.01)])
+    say("fast fp32 %d solves to tol 1e-6" % len(insts))
+    res = mmot.solve_batch(insts, precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
+    for d, r in zip(insts, res):
+        assert r["status"] == 0, (d["l"], d["N"], d["eps"], r)
+        err = fastcheck.marginal_errors(d["u"], d["log_phi"].cpu().numpy(), d["h"], d["eps"])
+        # the reported residual is the FP64 one of the returned potentials
+        assert abs(r["marg_err"] - err[:-1].sum()) <= 1e-9 + 1e-6 * err[:-1].sum(), (d["l"], d["N"], r, err)
+        assert err[:-1].sum() <= 1e-6, (d["l"], d["N"], d["eps"], err)
+        ref = fastcheck.objective(d["log_phi"].cpu().numpy(), d["h"], d["eps"])
+        assert abs(r["W"] - ref) <= 1e-10 * abs(ref), (d["l"], d["N"])
+
+
+def _wild(l, N, seed, decades):
+    # marginals whose neighbouring entries differ by up to 10^decades: the
+    # potentials of one thread's positions then span more exponent range than
+    # block floating point allows, and the solve moves to the extended-range solver
+    rng = np.random.default_rng(seed)
+    u = np.exp(rng.uniform(-decades * np.log(10.0), 0.0, size=(l, N)))
+    return u / u.sum(axis=1, keepdims=True)
+
+
+def test_fast_hands_over_wide_range_fp64():
+    mmot = _mmot()
+    insts = []
+    for (l, N) in [(3, 300), (4, 1000)]:
+        u = _wild(l, N, seed=l, decades=80)
+        insts.append(dict(l=l, N=N, h=inputs.grid_step(N), eps=0.05, u=u))
+    _dev(insts)
+    say("fast fp64 hand-over, 20 sweeps")
+    res = mmot.solve_batch(insts, precision=mmot.FP64, tol=-1.0, itr_max=20, check_every=0)
+    for d, r in zip(insts, res):
+        ref = fastcheck.sinkhorn(d["u"], d["h"], d["eps"], itmax=20, check_every=20)
+        assert r["iters"] == 20 and r["status"] == 0, r
+        assert potentials_err(d["log_phi"].cpu().numpy(), ref["log_phi"]) < FP64_TOL
+        assert abs(r["W"] - ref["W"]) <= FP64_TOL * abs(ref["W"])
+
+
+def test_fast_hands_over_wide_range_fp32():
+    mmot = _mmot()
+    insts = []
+    for (l, N) in [(3, 300), (4, 1000)]:
+        u = _wild(l, N, seed=10 + l, decades=8)
+        insts.append(dict(l=l, N=N, h=inputs.grid_step(N), eps=0.05, u=u))
+    _dev(insts)
+    say("fast fp32 hand-over, to tol 1e-6")
+    res = mmot.solve_batch(insts, precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
+    for d, r in zip(insts, res):
+        assert r["status"] == 0, r
+        err = fastcheck.marginal_errors(d["u"], d["log_phi"].cpu().numpy(), d["h"], d["eps"])
+        assert err[:-1].sum() <= 1e-6, err
