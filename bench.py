@@ -115,10 +115,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=1024)
+    ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 256 MiB device buffer 4 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 256 << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n, "launches": 4}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: instances are independent and would shard across GPUs "
               "with no communication; run with --gpus 1", file=sys.stderr)
@@ -214,11 +226,12 @@ def main():
         out["fp64"] = dict(value=units_of(r64) / t64, tol=tol64, seconds=t64,
                            all_converged=all(r["status"] == 0 for r in r64),
                            kernel_ms=mmot.last_batch_kernel_ms())
-        # the extended-range solver on the same batch (one wavefront per instance)
-        (rx, tx) = timed(lambda: step(mmot.FP32, tol32, fast=False))
-        out["extended_range_solver"] = dict(value=units_of(rx) / tx, seconds=tx,
-                                            all_converged=all(r["status"] == 0 for r in rx),
-                                            speedup_of_fast_path=value / (units_of(rx) / tx))
+        if sweep_launches > 0:
+            # the extended-range solver on the same batch (one wavefront per instance)
+            (rx, tx) = timed(lambda: step(mmot.FP32, tol32, fast=False))
+            out["extended_range_solver"] = dict(value=units_of(rx) / tx, seconds=tx,
+                                                all_converged=all(r["status"] == 0 for r in rx),
+                                                speedup_of_fast_path=value / (units_of(rx) / tx))
         # plain form: one solve per call, same accuracy, a subset of the batch
         nplain = min(16, args.instances)
         plans = [mmot.Plan(4, 1000, batch[i]["h"], batch[i]["eps"], precision=mmot.FP32, tol=tol32,
