@@ -128,7 +128,7 @@ constexpr int vsel(int l, int kind)
 // per workgroup by l and precision (1: FP32 sweeps, 0: FP64); an instance fits if
 // N <= fast_threads * fast_v.
 constexpr int FAST_MAXL = 4;            // largest l the fast path is built for
-constexpr bool FAST_PATH_ENABLED = false;  // host routing to the fast path (see fast_eligible)
+constexpr bool FAST_PATH_ENABLED = true;  // host routing to the fast path (see fast_eligible)
 constexpr int fast_v(int l, int precision)
 {
     return precision == 1 ? (l <= 4 ? 4 : l == 5 ? 2 : 1) : (l <= 4 ? 2 : 1);

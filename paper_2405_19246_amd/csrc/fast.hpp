@@ -28,13 +28,6 @@ namespace mmot {
 
 constexpr int FAST_MAXW = 16;  // wavefronts per workgroup at most
 
-// Discount factors as plain values with a hi + lo mantissa (0 when they fall
-// below the mantissa type's normal range: their contribution is negligible).
-template <typename M>
-struct GV {
-    M hi, lo;
-};
-
 template <typename M, int L, int V>
 struct FastConst {
     XG<M> g[L];                 // g(k) as an extended-range factor
@@ -44,23 +37,6 @@ struct FastConst {
     XG<M> gwave[L][FAST_MAXW];  // g(k)^(64 V d): wavefronts
     XG<M> glane[L][WAVE];       // g(k)^(V s): carry to the s-th lane in scan order
 };
-
-template <typename M>
-__device__ __forceinline__ GV<M> gv_from_log(double a)
-{
-    const double v = exp(a);
-    const M hi = (M)v;
-    const M lo = (M)(v - (double)hi);
-    constexpr double tiny = sizeof(M) == 4 ? 1.0e-37 : 1.0e-300;
-    if (!(v > tiny)) return {M(0), M(0)};
-    return {hi, lo};
-}
-
-template <typename M>
-__device__ __forceinline__ M gmul(GV<M> g, M x, M add)
-{
-    return fma(x, g.hi, fma(x, g.lo, add));
-}
 
 // Fill the constants (block-cooperative; caller syncs).
 template <typename M, int L, int V>
@@ -82,28 +58,6 @@ __device__ void fast_consts(FastConst<M, L, V> &C, double hoe, int tid, int nthr
             C.glane[k][sl] = xg_from_log<M>(lg * (double)(V * sl));
         }
     }
-}
-
-// Block-floating-point row of scaling factors phi = exp(a) at a thread's V
-// positions: mantissas m[v] (relative to 2^e) and the exponent e; returns the
-// exponent spread of the finite entries (0 if none).
-template <typename M, int V>
-__device__ __forceinline__ int bf_row(const double (&a)[V], M (&m)[V], int &e)
-{
-    XF<M> x[V];
-    int hi = XF_ZERO_E, lo = -XF_ZERO_E;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        x[v] = xfrom_log<M>(a[v]);
-        if (x[v].m != M(0)) {
-            hi = max(hi, x[v].e);
-            lo = min(lo, x[v].e);
-        }
-    }
-    e = hi;
-#pragma unroll
-    for (int v = 0; v < V; ++v) m[v] = xldexp(x[v].m, x[v].e - hi);
-    return hi >= lo ? hi - lo : 0;
 }
 
 // Block-wide FP64 sum (same value in every thread); uses red[0..FAST_MAXW).
@@ -129,14 +83,6 @@ __device__ __forceinline__ bool block_any(bool p, int *fl, int &phase, int lane,
     for (int i = 0; i < nw; ++i) r |= fl[phase * FAST_MAXW + i];
     phase ^= 1;
     return r != 0;
-}
-
-// Extended value with a normalised mantissa; zero gets the zero exponent.
-template <typename M>
-__device__ __forceinline__ XF<M> xnorm(XF<M> x)
-{
-    if (x.m == M(0)) return xzero<M>();
-    return {xmant(x.m), x.e + xexpo(x.m)};
 }
 
 // One direction of the level-synchronous scan over the whole instance chunk.

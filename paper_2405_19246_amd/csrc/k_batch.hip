@@ -12,9 +12,7 @@ __global__ __launch_bounds__(256) void k_objective_batch(const Inst *I, const Pt
 {
     const int lane = threadIdx.x & (WAVE - 1);
     for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(ticket, 1);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        const int t = wave_ticket(ticket, lane);
         if (t >= count) break;
         const int idx = __builtin_amdgcn_readfirstlane(list[t]);
         switch (I[idx].l) {

@@ -112,6 +112,18 @@ __device__ void solve_dispatch(const Inst *I, const Ptrs P, const RunOpts o, Res
     }
 }
 
+// Next instance ticket of a wavefront, the same value in every lane.  Every
+// lane takes part in one atomic (lane 0 adds 1, the others 0) and the value
+// lane 0 got is broadcast: no branch on the lane index precedes the
+// broadcast.  (With the atomic under `if (lane == 0)` and a shuffle
+// broadcast, the optimizer can send the other lanes round the loop past the
+// atomic with a constant 0 as their shuffle input; they then take ticket 0
+// forever and the wavefront never leaves the loop.)
+__device__ __forceinline__ int wave_ticket(int *ticket, int lane)
+{
+    return __builtin_amdgcn_readfirstlane(atomicAdd(ticket, lane == 0 ? 1 : 0));
+}
+
 // Persistent batch: wavefronts pull instance tickets until none is left.
 template <typename M>
 __global__ __launch_bounds__(256, 2) void k_solve_batch(const Inst *I, const Ptrs *P, const int *order, int count,
@@ -119,9 +131,7 @@ __global__ __launch_bounds__(256, 2) void k_solve_batch(const Inst *I, const Ptr
 {
     const int lane = threadIdx.x & (WAVE - 1);
     for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(ticket, 1);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        const int t = wave_ticket(ticket, lane);
         if (t >= count) break;
         const int idx = __builtin_amdgcn_readfirstlane(order[t]);
         solve_dispatch<M>(&I[idx], P[idx], o, &R[idx], lane);

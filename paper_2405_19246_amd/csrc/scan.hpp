@@ -117,6 +117,209 @@ __device__ __forceinline__ void level_scan(const XF<typename ET<E>::MT> (&phi)[L
     }
 }
 
+// ---- FP32 scans in block floating point -------------------------------------
+//
+// Same recurrences as level_scan, but inside one lane the V values of a row or
+// of a state share one exponent: the inflow sums and the in-lane discounted
+// scan are plain FP32 FMAs on mantissas, and extended-range values are only
+// formed where a lane hands its aggregate on (Kogge-Stone across lanes, the
+// chunk carry).  Exact up to FP32 rounding while the values of one lane span
+// less exponent range than FP32 holds next to each other (bf_fits_range).
+// Discount factors keep their hi + lo mantissa everywhere, as in level_scan.
+
+// Plain hi + lo value of a discount factor held as an extended-range one.
+__device__ __forceinline__ GV<float> gv_of(const XG<float> &g) { return {xldexp(g.hi, g.e), xldexp(g.lo, g.e)}; }
+
+// Decay of the discount factors per grid position, in bits.
+template <int L>
+__device__ __forceinline__ int disc_decay_bits(const Disc<float> *__restrict__ K)
+{
+    int dec = 0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) dec = max(dec, 1 - K->g1[k].e);
+    return dec;
+}
+
+//   pm/pe  rows of R's members at the lane's positions: mantissas relative to 2^pe[r]
+//   Fm/Fe  out: states, mantissas relative to 2^Fe[S]; the largest |Fm[S][.]| is
+//          in [1/4, 2], or all are 0 and Fe[S] is the zero exponent
+//   cin    out: state at the position before the lane's first one (scan order)
+//   carry  in: state at the position before the chunk; out: at the chunk's last one
+//   lanep  g(k)^(V * scan lane)
+template <int L, int V, bool FWD>
+__device__ __forceinline__ void level_scan_bf(const float (&pm)[L - 1][V], const int (&pe)[L - 1],
+                                              float (&Fm)[1 << (L - 1)][V], int (&Fe)[1 << (L - 1)],
+                                              XF<float> (&cin)[1 << (L - 1)], XF<float> (&carry)[1 << (L - 1)],
+                                              const Disc<float> *__restrict__ K, const XG<float> (&lanep)[L], int sl)
+{
+    constexpr int n = L - 1;
+    constexpr int D = 1 << n;
+
+#pragma unroll
+    for (int k = 1; k <= n; ++k) {
+        const GV<float> gk = gv_of(K->g1[k]);
+        float loc[D][V];
+        int Ein[D];
+#pragma unroll
+        for (int S = 1; S < D; ++S) {
+            if (popc(S) != k) continue;
+            // exponent bound of each inflow term T (members placed at this position)
+            int Et[D];
+            int E = XF_ZERO_E;
+#pragma unroll
+            for (int T = 1; T < D; ++T) {
+                if ((T & S) != T) continue;
+                int et = 0;
+#pragma unroll
+                for (int r = 0; r < n; ++r)
+                    if (T & (1 << r)) et += pe[r];
+                const int Sp = S ^ T;
+                if (Sp) et += Fe[Sp] + K->g1[popc(Sp)].e;
+                Et[T] = et;
+                E = max(E, et);
+            }
+            // its coefficient g(|S\T|) 2^(Et - E), hi + lo
+            float ch[D], cl[D];
+#pragma unroll
+            for (int T = 1; T < D; ++T) {
+                if ((T & S) != T) continue;
+                const int Sp = S ^ T;
+                ch[T] = xldexp(Sp ? K->g1[popc(Sp)].hi : 1.0f, Et[T] - E);
+                cl[T] = Sp ? xldexp(K->g1[popc(Sp)].lo, Et[T] - E) : 0.0f;
+            }
+            // lower-level states before the lane's first position, as mantissas
+            float cm[D];
+#pragma unroll
+            for (int Sp = 1; Sp < D; ++Sp)
+                if ((Sp & S) == Sp && Sp != S) cm[Sp] = xldexp(cin[Sp].m, cin[Sp].e - Fe[Sp]);
+            float mx = 0.0f;
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                const int v = FWD ? t : V - 1 - t;
+                const int vp = FWD ? v - 1 : v + 1;
+                float in = 0.0f;
+#pragma unroll
+                for (int T = 1; T < D; ++T) {
+                    if ((T & S) != T) continue;
+                    float pp = 1.0f;
+#pragma unroll
+                    for (int r = 0; r < n; ++r)
+                        if (T & (1 << r)) pp *= pm[r][v];
+                    const int Sp = S ^ T;
+                    if (Sp == 0) {
+                        in = fmaf(ch[T], pp, in);
+                    } else {
+                        const float prev = (t == 0) ? cm[Sp] : Fm[Sp][vp];
+                        in = fmaf(fmaf(cl[T], prev, ch[T] * prev), pp, in);
+                    }
+                }
+                loc[S][v] = (t == 0) ? in : gmul(gk, loc[S][vp], in);
+                mx = fmaxf(mx, loc[S][v]);
+            }
+            // tighten the exponent to the values actually there (all zero: zero exponent)
+            Ein[S] = (mx == 0.0f) ? XF_ZERO_E : E;
+            if (mx != 0.0f) {
+                const int d = xexpo(mx);
+                Ein[S] += d;
+#pragma unroll
+                for (int v = 0; v < V; ++v) loc[S][v] = xldexp(loc[S][v], -d);
+            }
+        }
+        // carries of level k across lanes and from the previous chunk
+#pragma unroll
+        for (int S = 1; S < D; ++S) {
+            if (popc(S) != k) continue;
+            XF<float> incl = xnorm(XF<float>{loc[S][FWD ? V - 1 : 0], Ein[S]});
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const int d = 1 << s;
+                XF<float> o;
+                if (FWD) o = {__shfl_up(incl.m, d), __shfl_up(incl.e, d)};
+                else o = {__shfl_down(incl.m, d), __shfl_down(incl.e, d)};
+                if (sl >= d) incl = xadd(incl, xmulg(o, K->gstep[k][s]));
+            }
+            XF<float> ex;
+            if (FWD) ex = {__shfl_up(incl.m, 1), __shfl_up(incl.e, 1)};
+            else ex = {__shfl_down(incl.m, 1), __shfl_down(incl.e, 1)};
+            XF<float> c = xmulg(carry[S], lanep[k]);
+            if (sl > 0) c = xadd(ex, c);
+            c = xnorm(c);
+            cin[S] = c;
+            // block exponent of the state: the larger of the local part and the carry part
+            const int ec = (c.m == 0.0f) ? XF_ZERO_E : c.e + K->g1[k].e;
+            const int F = max(Ein[S], ec);
+            Fe[S] = F;
+            const float sc = xldexp(1.0f, Ein[S] - F);
+            const float cmk = xldexp(c.m, c.e - F);
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                const int v = FWD ? t : V - 1 - t;
+                Fm[S][v] = gmul(gv_of(K->gfix[k][t]), cmk, loc[S][v] * sc);
+            }
+            const XF<float> last = xnorm(XF<float>{Fm[S][FWD ? V - 1 : 0], F});
+            carry[S] = {rlane(last.m, FWD ? WAVE - 1 : 0), rlane(last.e, FWD ? WAVE - 1 : 0)};
+        }
+    }
+}
+
+// log J_j at the lane's positions from both scans of a chunk (natural log, FP64):
+// J(y) = sum_S F_y(S) g(|R\S|) B_{y+1}(R\S).
+template <int L, int V>
+__device__ __forceinline__ void combine_bf(const float (&Fm)[1 << (L - 1)][V], const int (&Fe)[1 << (L - 1)],
+                                           const float (&Bm)[1 << (L - 1)][V], const int (&Be)[1 << (L - 1)],
+                                           const XF<float> (&cinB)[1 << (L - 1)], const Disc<float> *__restrict__ K,
+                                           double (&lj)[V])
+{
+    constexpr int D = 1 << (L - 1);
+    if (V > 1) {
+        // positions v < V-1: the next position's backward state is in this lane
+        int TE[D];
+        int E = XF_ZERO_E;
+#pragma unroll
+        for (int S = 0; S < D; ++S) {
+            const int U = (D - 1) ^ S;
+            TE[S] = (S ? Fe[S] : 0) + (U ? Be[U] + K->g1[popc(U)].e : 0);
+            E = max(E, TE[S]);
+        }
+        float ch[D], cl[D];
+#pragma unroll
+        for (int S = 0; S < D; ++S) {
+            const int U = (D - 1) ^ S;
+            ch[S] = xldexp(U ? K->g1[popc(U)].hi : 1.0f, TE[S] - E);
+            cl[S] = U ? xldexp(K->g1[popc(U)].lo, TE[S] - E) : 0.0f;
+        }
+#pragma unroll
+        for (int v = 0; v < V - 1; ++v) {
+            float jv = 0.0f;
+#pragma unroll
+            for (int S = 0; S < D; ++S) {
+                const int U = (D - 1) ^ S;
+                const float t = (S ? Fm[S][v] : 1.0f) * (U ? Bm[U][v + 1] : 1.0f);
+                jv = fmaf(ch[S], t, fmaf(cl[S], t, jv));
+            }
+            lj[v] = (jv == 0.0f) ? -INFINITY : xto_log(XF<float>{jv, E});
+        }
+    }
+    // the lane's last position: the next position's backward state is its carry-in
+    int TE[D];
+    int E = XF_ZERO_E;
+#pragma unroll
+    for (int S = 0; S < D; ++S) {
+        const int U = (D - 1) ^ S;
+        TE[S] = (S ? Fe[S] : 0) + (U ? cinB[U].e + K->g1[popc(U)].e : 0);
+        E = max(E, TE[S]);
+    }
+    float jv = 0.0f;
+#pragma unroll
+    for (int S = 0; S < D; ++S) {
+        const int U = (D - 1) ^ S;
+        const float f = xldexp(S ? Fm[S][V - 1] : 1.0f, TE[S] - E);
+        const float b = U ? fmaf(cinB[U].m, K->g1[popc(U)].lo, cinB[U].m * K->g1[popc(U)].hi) : 1.0f;
+        jv = fmaf(f, b, jv);
+    }
+    lj[V - 1] = (jv == 0.0f) ? -INFINITY : xto_log(XF<float>{jv, E});
+}
+
 // Result.status values set on the device.
 static constexpr int ST_OK = 0;
 static constexpr int ST_NUMERIC = -3;
@@ -160,6 +363,30 @@ __device__ __forceinline__ XF<double> wave_sum_xf(XF<double> x)
     return {rlane(x.m, 0), rlane(x.e, 0)};
 }
 
+// What a product, update or check pass does with log J_j at position p; returns
+// the position's contribution to the pass's sum.
+//   P_PRODUCT: out[p] = log J_j(p)
+//   P_UPDATE:  a_j(p) = log u_j(p) - log J_j(p); returns u_j(p) |exp(a_old - a_new) - 1|
+//   P_CHECK:   returns |exp(a_j(p) + log J_j(p)) - u_j(p)|
+template <int MODE>
+__device__ __forceinline__ double finish_lj(double lj, int j, long N, long p, double *__restrict__ a,
+                                            const double *__restrict__ log_u, double *__restrict__ out)
+{
+    if constexpr (MODE == P_PRODUCT) {
+        out[p] = lj;
+        return 0.0;
+    } else if constexpr (MODE == P_UPDATE) {
+        const double lu = log_u[(long)j * N + p];
+        const double ao = a[(long)j * N + p];
+        const double an = lu > -INFINITY ? lu - lj : -INFINITY;
+        a[(long)j * N + p] = an;
+        return lu > -INFINITY ? exp(lu) * fabs(expm1(ao - an)) : 0.0;
+    } else {
+        const double lu = log_u[(long)j * N + p];
+        return fabs(exp(a[(long)j * N + p] + lj) - exp(lu));
+    }
+}
+
 // One marginal pass over an instance on one wavefront.
 //   P_PRODUCT:   out[y] = log J_j(y)
 //   P_UPDATE:    a_j(y) = log u_j(y) - log J_j(y)           (Gauss-Seidel step);
@@ -193,14 +420,32 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
 #pragma unroll
     for (int r = 0; r < n; ++r) items[r] = (r < j) ? r : r + 1;
 
-    auto load_phi = [&](long c, XF<M>(&phi)[n][V]) {
+    // FP32 products and updates take the block-floating-point scans for every
+    // chunk whose rows fit them (wavefront-uniform choice), the extended-range
+    // scans otherwise; both keep the chunk carries in extended range.
+    constexpr bool BF = std::is_same<E, XF<float>>::value && (MODE == P_PRODUCT || MODE == P_UPDATE);
+    auto load_a = [&](long c, double(&av)[n][V]) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const long p = c * CH + (long)lane * V + v;
 #pragma unroll
-            for (int r = 0; r < n; ++r)
-                phi[r][v] = (p < N) ? xfrom_log<M>(a[(long)items[r] * N + p]) : xzero<M>();
+            for (int r = 0; r < n; ++r) av[r][v] = (p < N) ? a[(long)items[r] * N + p] : -INFINITY;
         }
+    };
+    auto to_phi = [&](const double(&av)[n][V], XF<M>(&phi)[n][V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int r = 0; r < n; ++r) phi[r][v] = xfrom_log<M>(av[r][v]);
+    };
+    // rows in block floating point; true if every lane's values fit
+    int dec = 0;
+    if constexpr (BF) dec = disc_decay_bits<L>(K);
+    auto to_bf = [&](const double(&av)[n][V], float(&pm)[n][V], int(&pe)[n]) {
+        int sp = 0;
+#pragma unroll
+        for (int r = 0; r < n; ++r) sp = max(sp, bf_row<float, V>(av[r], pm[r], pe[r]));
+        return __ballot(!bf_fits_range(1, L, V, sp, dec)) == 0;
     };
 
     E carryF[D], carryB[D];
@@ -212,10 +457,23 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
     // forward sweep over chunks, saving each chunk's carry-in (only if >1 chunk)
     if (C > 1) {
         for (long c = 0; c < C; ++c) {
-            XF<M> phi[n][V];
-            load_phi(c, phi);
+            double av[n][V];
+            load_a(c, av);
 #pragma unroll
             for (int S = 1; S < D; ++S) store_elem(scratch, c * (D - 1) + (S - 1), lane == 0, carryF[S]);
+            if constexpr (BF) {
+                float pm[n][V];
+                int pe[n];
+                if (to_bf(av, pm, pe)) {
+                    float Fm[D][V];
+                    int Fe[D];
+                    XF<float> cin[D];
+                    level_scan_bf<L, V, true>(pm, pe, Fm, Fe, cin, carryF, K, lanepF, slF);
+                    continue;
+                }
+            }
+            XF<M> phi[n][V];
+            to_phi(av, phi);
             E st[D][V], cin[D];
             level_scan<L, V, E, true>(phi, st, cin, carryF, K, lanepF, (double)slF, slF);
         }
@@ -226,12 +484,33 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
     double acc = 0.0;
     XF<double> accx = xzero<double>();
     for (long c = C - 1; c >= 0; --c) {
-        XF<M> phi[n][V];
-        load_phi(c, phi);
+        double av[n][V];
+        load_a(c, av);
         if (C > 1) {
 #pragma unroll
             for (int S = 1; S < D; ++S) carryF[S] = reinterpret_cast<const E *>(scratch)[c * (D - 1) + (S - 1)];
         }
+        if constexpr (BF) {
+            float pm[n][V];
+            int pe[n];
+            if (to_bf(av, pm, pe)) {
+                float Fm[D][V], Bm[D][V];
+                int Fe[D], Be[D];
+                XF<float> cinF[D], cinB[D];
+                level_scan_bf<L, V, true>(pm, pe, Fm, Fe, cinF, carryF, K, lanepF, slF);
+                level_scan_bf<L, V, false>(pm, pe, Bm, Be, cinB, carryB, K, lanepB, slB);
+                double ljv[V];
+                combine_bf<L, V>(Fm, Fe, Bm, Be, cinB, K, ljv);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const long p = c * CH + (long)lane * V + v;
+                    if (p < N) acc += finish_lj<MODE>(ljv[v], j, N, p, a, log_u, out);
+                }
+                continue;
+            }
+        }
+        XF<M> phi[n][V];
+        to_phi(av, phi);
         E F[D][V], cinF[D];
         level_scan<L, V, E, true>(phi, F, cinF, carryF, K, lanepF, (double)slF, slF);
         E B[D][V], cinB[D];
@@ -259,20 +538,7 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
                     const XF<double> ph = xfrom_log<double>(a[(long)j * N + p]);
                     accx = xadd(accx, xmul(ph, J.w));
                 } else {
-                    const double lj = xto_log(J);
-                    if constexpr (MODE == P_PRODUCT) {
-                        out[p] = lj;
-                    } else if constexpr (MODE == P_UPDATE) {
-                        // marginal error this update removes: u |exp(a_old - a_new) - 1|
-                        const double lu = log_u[(long)j * N + p];
-                        const double ao = a[(long)j * N + p];
-                        const double an = lu > -INFINITY ? lu - lj : -INFINITY;
-                        if (lu > -INFINITY) acc += exp(lu) * fabs(expm1(ao - an));
-                        a[(long)j * N + p] = an;
-                    } else {
-                        const double lu = log_u[(long)j * N + p];
-                        acc += fabs(exp(a[(long)j * N + p] + lj) - exp(lu));
-                    }
+                    acc += finish_lj<MODE>(xto_log(J), j, N, p, a, log_u, out);
                 }
             }
         }

@@ -79,9 +79,6 @@ size_t scratch_bytes(int l, int64_t N, int precision)
 
 bool fast_eligible(const Inst &I, int precision)
 {
-    // Switched off: the first GPU run of the register-resident path did not
-    // finish (no fault reported); its cause has not been found, so no solve is
-    // routed there until it is.
     if (!FAST_PATH_ENABLED) return false;
     const int l = I.l;
     if (l < 2 || l > FAST_MAXL) return false;

@@ -7,9 +7,7 @@ from gpu_util import potentials_err, say, to_dev
 from oracle import fastcheck
 from paper_2405_19246_amd import inputs
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="register-resident path switched off: its first GPU run did not finish "
-                                      "and the cause is not found yet")]
+pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
 
@@ -48,7 +46,9 @@ def test_fast_fp64_fixed_sweeps_match_oracle(eps):
         assert r["iters"] == 25 and r["status"] == 0, (d["l"], d["N"], r)
         assert potentials_err(got, ref["log_phi"]) < FP64_TOL, (d["l"], d["N"], potentials_err(got, ref["log_phi"]))
         assert abs(r["W"] - ref["W"]) <= FP64_TOL * abs(ref["W"]) + 1e-300, (d["l"], d["N"])
-        assert abs(r["marg_err"] - ref["res"]) <= 1e-9 * ref["res"] + 1e-15, (d["l"], d["N"])
+        # Res sums |phi J - u| over the grid, differences of nearly equal numbers:
+        # its absolute error is a few ulps of the total mass (1), whatever Res is
+        assert abs(r["marg_err"] - ref["res"]) <= 1e-9 * ref["res"] + 16 * 2.0 ** -52, (d["l"], d["N"])
 
 
 def test_fast_fp64_equals_extended_range_solver():
