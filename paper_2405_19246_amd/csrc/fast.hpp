@@ -165,23 +165,21 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
                 for (int v = 0; v < V; ++v) loc[S][v] = xldexp(loc[S][v], -d);
             }
         }
-        // lanes: Kogge-Stone on the thread aggregates (extended range)
+        // lanes: Kogge-Stone on the thread aggregates (extended range), DPP moves
         XF<M> excl[D];
 #pragma unroll
         for (int S = 1; S < D; ++S) {
             if (popc(S) != k) continue;
-            XF<M> incl = xnorm(XF<M>{loc[S][FWD ? V - 1 : 0], Ein[S]});
-#pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                const int d = 1 << s;
-                XF<M> o;
-                if (FWD) o = {__shfl_up(incl.m, d), __shfl_up(incl.e, d)};
-                else o = {__shfl_down(incl.m, d), __shfl_down(incl.e, d)};
-                if (sl >= d) incl = xadd(incl, xmulg(o, C.gstep[k][s]));
+            const XF<M> a = xnorm(XF<M>{loc[S][FWD ? V - 1 : 0], Ein[S]});
+            XF<M> incl;
+            if (FWD) {
+                incl = ks_up_dpp(a, C.gstep[k], C.glane[k], lane);
+                excl[S] = dpp_xf<0x138>(incl);  // wave_shr:1, zero in lane 0
+            } else {
+                incl = ks_down_dpp(a, C.gstep[k], C.glane[k], lane);
+                excl[S] = dpp_xf<0x130>(incl);  // wave_shl:1, zero in lane 63
             }
-            if (FWD) excl[S] = {__shfl_up(incl.m, 1), __shfl_up(incl.e, 1)};
-            else excl[S] = {__shfl_down(incl.m, 1), __shfl_down(incl.e, 1)};
-            const XF<M> wagg = {rlane(incl.m, FWD ? WAVE - 1 : 0), rlane(incl.e, FWD ? WAVE - 1 : 0)};
+            const XF<M> wagg = rlane_xf(incl, FWD ? WAVE - 1 : 0);
             if (lane == 0) xw[(half * FAST_MAXW + sw) * D + S] = xnorm(wagg);
         }
         __syncthreads();
@@ -192,9 +190,7 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
             XF<M> wc = xzero<M>();
             for (int w = 0; w < sw; ++w)  // slots are indexed in scan order
                 wc = xadd(wc, xmulg(xw[(half * FAST_MAXW + w) * D + S], C.gwave[k][sw - 1 - w]));
-            XF<M> c = xmulg(wc, C.glane[k][sl]);
-            if (sl > 0) c = xadd(excl[S], c);
-            c = xnorm(c);
+            const XF<M> c = xnorm(xadd(excl[S], xmulg(wc, C.glane[k][sl])));
             cin[S] = c;
             // block exponent of the state: the larger of the local part and the carry part
             const int ec = c.m == M(0) ? XF_ZERO_E : c.e + C.g[k].e;

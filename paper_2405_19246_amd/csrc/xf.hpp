@@ -168,6 +168,77 @@ __device__ __forceinline__ int bf_row(const double (&a)[V], M (&m)[V], int &e)
 }
 
 
+// DPP lane moves (GFX9 controls, checked on the device): lanes without a
+// source lane, or in rows outside ROWMASK, get `old`.
+//   0x101..0x108 row_shl:1..8 and 0x111..0x118 row_shr:1..8 (within rows of 16
+//   lanes), 0x130 wave_shl:1, 0x138 wave_shr:1, 0x142 row_bcast:15 (lane 15 of
+//   each row to the next row), 0x143 row_bcast:31 (lane 31 to rows 2 and 3).
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ int dpp_i(int old, int x)
+{
+    return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xF, false);
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ float dpp_m(float x)
+{
+    return __int_as_float(dpp_i<CTRL, ROWMASK>(0, __float_as_int(x)));
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_m(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_i<CTRL, ROWMASK>(0, (int)(b & 0xffffffffLL));
+    const int hi = dpp_i<CTRL, ROWMASK>(0, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// An extended value moved by DPP; lanes without a source get zero.
+template <int CTRL, int ROWMASK = 0xF, typename M>
+__device__ __forceinline__ XF<M> dpp_xf(XF<M> x)
+{
+    return {dpp_m<CTRL, ROWMASK>(x.m), dpp_i<CTRL, ROWMASK>(XF_ZERO_E, x.e)};
+}
+
+// Inclusive scan of per-lane aggregates towards higher lanes under the
+// operator (a over w positions) . b = g^(V w) a + b, DPP moves only: shifts by
+// 1, 2, 4, 8 inside rows of 16 lanes, then lane 15 of each row to the next row
+// and lane 31 to the upper half.  gstep[s] = g^(V 2^s); glane[s] = g^(V s).
+template <typename M>
+__device__ __forceinline__ XF<M> ks_up_dpp(XF<M> x, const XG<M> *gstep, const XG<M> *glane, int lane)
+{
+    x = xadd(x, xmulg(dpp_xf<0x111>(x), gstep[0]));
+    x = xadd(x, xmulg(dpp_xf<0x112>(x), gstep[1]));
+    x = xadd(x, xmulg(dpp_xf<0x114>(x), gstep[2]));
+    x = xadd(x, xmulg(dpp_xf<0x118>(x), gstep[3]));
+    x = xadd(x, xmulg(dpp_xf<0x142, 0xA>(x), glane[(lane & 15) + 1]));
+    x = xadd(x, xmulg(dpp_xf<0x143, 0xC>(x), glane[lane >= 32 ? lane - 31 : 0]));
+    return x;
+}
+
+template <typename M>
+__device__ __forceinline__ XF<M> rlane_xf(XF<M> x, int l)
+{
+    return {rlane(x.m, l), rlane(x.e, l)};
+}
+
+// The same scan towards lower lanes: shifts inside rows of 16 lanes, then the
+// totals from the first lane of rows 1, 2, 3 to the last lane (read as
+// wavefront-uniform values) carried into the rows below.
+template <typename M>
+__device__ __forceinline__ XF<M> ks_down_dpp(XF<M> x, const XG<M> *gstep, const XG<M> *glane, int lane)
+{
+    x = xadd(x, xmulg(dpp_xf<0x101>(x), gstep[0]));
+    x = xadd(x, xmulg(dpp_xf<0x102>(x), gstep[1]));
+    x = xadd(x, xmulg(dpp_xf<0x104>(x), gstep[2]));
+    x = xadd(x, xmulg(dpp_xf<0x108>(x), gstep[3]));
+    const XF<M> t3 = rlane_xf(x, 48);
+    const XF<M> t2 = xadd(rlane_xf(x, 32), xmulg(t3, glane[16]));
+    const XF<M> t1 = xadd(rlane_xf(x, 16), xmulg(t2, glane[16]));
+    const int r = lane >> 4;
+    const XF<M> t = r == 0 ? t1 : r == 1 ? t2 : r == 2 ? t3 : xzero<M>();
+    return xadd(x, xmulg(t, glane[16 - (lane & 15)]));
+}
+
+
 // ---- element kinds used by the scans ----
 // XF<M>: plain value.  DXF: (value, cost-weighted value) for the objective.
 struct DXF {
