@@ -92,6 +92,45 @@ def traffic_entry(sha: str):
     return t
 
 
+def _pmc_sum(run_dir: str, kernel_prefix: str):
+    """Sum of the one counter of a rocprofv3 --pmc run over the dispatches of a kernel, and their count."""
+    import csv
+    tot, n = 0.0, 0
+    with open(os.path.join(run_dir, "run_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r["Kernel_Name"].startswith(kernel_prefix):
+                tot += float(r["Counter_Value"])
+                n += 1
+    return tot, n
+
+
+def write_traffic(root: str):
+    """Calibrated HBM bytes per launch of the sweep kernel: FETCH_SIZE and WRITE_SIZE (KiB) each scaled
+    by true bytes / counter reading of a plain 256 MiB device copy, over the sweep launches of a
+    one-step bench run; units per launch from that run's own JSON line."""
+    kern, copy = "void mmot::k_fast_sweep<4, 4, float>", "__amd_rocclr_copyBuffer"
+    fetch, nf = _pmc_sum(os.path.join(root, "pmc_bench_FETCH_SIZE"), kern)
+    write, nw = _pmc_sum(os.path.join(root, "pmc_bench_WRITE_SIZE"), kern)
+    cf, ncf = _pmc_sum(os.path.join(root, "pmc_copy_FETCH_SIZE"), copy)
+    cw, ncw = _pmc_sum(os.path.join(root, "pmc_copy_WRITE_SIZE"), copy)
+    true_kib = (256 << 20) / 1024.0
+    fs, ws = true_kib / (cf / ncf), true_kib / (cw / ncw)
+    line = [ln for ln in open(os.path.join(root, "pmc_bench_FETCH_SIZE.log")) if ln.startswith('{"metric"')][-1]
+    d = json.loads(line)
+    upl = d["roofline"]["units_per_launch"]
+    bpl = (fetch / nf * fs + write / nw * ws) * 1024.0
+    out = dict(kernel="k_fast_sweep<4,4,float>", workload=d["config"]["workload"],
+               kernel_src_sha1=d["kernel_src_sha1"], launches=nf,
+               fetch_kib_per_launch_raw=fetch / nf, write_kib_per_launch_raw=write / nw,
+               copy_fetch_kib_raw=cf / ncf, copy_write_kib_raw=cw / ncw, copy_kib_true=true_kib,
+               fetch_scale=fs, write_scale=ws, hbm_bytes_per_launch=bpl, units_per_launch=upl,
+               hbm_bytes_per_unit=bpl / upl, algorithmic_bytes_per_unit=24)
+    path = os.path.join(ROOT, "profiles", "traffic_l4_n1000.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(seconds: float):
     """The oracle (FP64 C checker, one thread) on instances of the same workload."""
     from oracle import fastcheck
@@ -120,7 +159,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 4 times (reference for HBM byte counters)")
+    ap.add_argument("--write-traffic", metavar="PMC_ROOT",
+                    help="write profiles/traffic_l4_n1000.json from the rocprofv3 --pmc runs under PMC_ROOT "
+                         "(pmc_bench_FETCH_SIZE, pmc_bench_WRITE_SIZE, pmc_copy_FETCH_SIZE, pmc_copy_WRITE_SIZE "
+                         "and their .log files); runs on the CPU")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
     if args.copy_calibration:
         import torch
         n = 256 << 20

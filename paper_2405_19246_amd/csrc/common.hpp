@@ -135,6 +135,10 @@ constexpr int fast_v(int l, int precision)
 }
 constexpr int fast_threads(int l, int precision) { return precision == 1 || l >= 6 ? 256 : 512; }
 constexpr long fast_capacity(int l, int precision) { return (long)fast_threads(l, precision) * fast_v(l, precision); }
+// Wavefronts per SIMD the FP32 sweep kernel is compiled for: three blocks of
+// four wavefronts per compute unit fit its LDS, and the registers then come to
+// 168 per lane (a few values of the outer loops spill).
+constexpr int fast_waves_per_eu(int precision) { return precision == 1 ? 3 : 1; }
 
 // Block floating point holds while the values one thread keeps span at most
 // this many bits: rows of l - 1 marginals (row_spread bits each), v positions

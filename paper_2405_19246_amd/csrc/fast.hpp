@@ -170,17 +170,17 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
 #pragma unroll
         for (int S = 1; S < D; ++S) {
             if (popc(S) != k) continue;
-            const XF<M> a = xnorm(XF<M>{loc[S][FWD ? V - 1 : 0], Ein[S]});
-            XF<M> incl;
+            const XB<M> a = xb_of(xnorm(XF<M>{loc[S][FWD ? V - 1 : 0], Ein[S]}));
+            XB<M> incl;
             if (FWD) {
                 incl = ks_up_dpp(a, C.gstep[k], C.glane[k], lane);
-                excl[S] = dpp_xf<0x138>(incl);  // wave_shr:1, zero in lane 0
+                excl[S] = xf_of(dpp_xb<0x138>(incl));  // wave_shr:1, zero in lane 0
             } else {
                 incl = ks_down_dpp(a, C.gstep[k], C.glane[k], lane);
-                excl[S] = dpp_xf<0x130>(incl);  // wave_shl:1, zero in lane 63
+                excl[S] = xf_of(dpp_xb<0x130>(incl));  // wave_shl:1, zero in lane 63
             }
-            const XF<M> wagg = rlane_xf(incl, FWD ? WAVE - 1 : 0);
-            if (lane == 0) xw[(half * FAST_MAXW + sw) * D + S] = xnorm(wagg);
+            const XF<M> wagg = xf_of(rlane_xb(incl, FWD ? WAVE - 1 : 0));
+            if (lane == 0) xw[(half * FAST_MAXW + sw) * D + S] = wagg;
         }
         __syncthreads();
         // wavefronts: carry into this wavefront from the earlier ones, then per lane
@@ -207,14 +207,25 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
     }
 }
 
-// log J_j at the thread's positions from the two scans (natural log, FP64).
-// The forward states come from LDS: fm[((S - 1) V + v) T + tid], fe[(S - 1) T + tid]
-// with T threads per workgroup.
-template <int L, int V, typename M>
+// Natural log of a combine result j 2^E (FP64; -inf for j = 0).
+template <typename M>
+__device__ __forceinline__ double jlog(M j, int E)
+{
+    if (j == M(0)) return -INFINITY;
+    if constexpr (sizeof(M) == 4)
+        return xlog_hw(j, E);
+    else
+        return xto_log(XF<M>{j, E});
+}
+
+// log J_j at the thread's positions from the two scans (natural log, FP64),
+// handed to at(v, log J_j) position by position.  The forward states come from
+// LDS: fm[((S - 1) V + v) T + tid], fe[(S - 1) T + tid] with T threads per
+// workgroup.
+template <int L, int V, typename M, typename At>
 __device__ __forceinline__ void bcombine(const M *fm, const int *fe, int tid, int T,
                                          const M (&Bm)[1 << (L - 1)][V], const int (&Be)[1 << (L - 1)],
-                                         const XF<M> (&cinB)[1 << (L - 1)], const FastConst<M, L, V> &C,
-                                         double (&lj)[V])
+                                         const XF<M> (&cinB)[1 << (L - 1)], const FastConst<M, L, V> &C, At &&at)
 {
     constexpr int D = 1 << (L - 1);
     int Fe[D];
@@ -246,7 +257,7 @@ __device__ __forceinline__ void bcombine(const M *fm, const int *fe, int tid, in
                 const M b = U ? Bm[U][v + 1] : M(1);
                 j = fma(cf[S] * f, b, j);
             }
-            lj[v] = (j == M(0)) ? -INFINITY : xto_log(XF<M>{j, E});
+            at(v, jlog(j, E));
         }
     }
     // last position: the next position's backward state is the carry into this thread
@@ -267,18 +278,19 @@ __device__ __forceinline__ void bcombine(const M *fm, const int *fe, int tid, in
             const M b = U ? cinB[U].m * C.g[popc(U)].hi : M(1);
             j = fma(xldexp(f, TE[S] - E), b, j);
         }
-        lj[V - 1] = (j == M(0)) ? -INFINITY : xto_log(XF<M>{j, E});
+        at(V - 1, jlog(j, E));
     }
 }
 
-// log J_j at the thread's positions (both scans + combine); rows 0 .. l-2 of
+// log J_j at the thread's positions (both scans + combine, handed to at(v, .));
+// rows 0 .. l-2 of
 // pm/pe are the l - 1 marginals other than j, in any order (the subset
 // dynamic program is symmetric in them).  The forward states wait in LDS
 // (fm, fe) while the backward scan runs.
-template <int L, int V, typename M>
+template <int L, int V, typename M, typename At>
 __device__ __forceinline__ void bproduct(const M (&pm)[L][V], const int (&pe)[L], const FastConst<M, L, V> &C,
                                          XF<M> *xw, M *fm, int *fe, int tid, int T, int lane, int wave, int nw,
-                                         double (&lj)[V])
+                                         At &&at)
 {
     constexpr int n = L - 1;
     constexpr int D = 1 << n;
@@ -298,18 +310,21 @@ __device__ __forceinline__ void bproduct(const M (&pm)[L][V], const int (&pe)[L]
     int Be[D];
     XF<M> cinB[D];
     bscan<L, V, M, false>(pm, pe, Bm, Be, cinB, C, xw, n, lane, wave, nw);
-    bcombine<L, V, M>(fm, fe, tid, T, Bm, Be, cinB, C, lj);
+    bcombine<L, V, M>(fm, fe, tid, T, Bm, Be, cinB, C, at);
 }
 
-template <typename M>
-__device__ __forceinline__ M mexpm1(M x)
+// One term u |exp(d) - 1| of the stopping estimate (d = a_old - a_new at a
+// position, u = exp(log_u) there), in FP32: it only decides when the FP64
+// residual is computed.  |d| <= 1/16: the cubic Taylor polynomial (relative
+// error below 1e-5); beyond, the polynomial is a lower bound for d > 0 and is
+// capped at 1 for d < 0 (where |exp(d) - 1| < 1).
+__device__ __forceinline__ double est_term(double lu, double d)
 {
-    if constexpr (sizeof(M) == 4) return expm1f(x); else return expm1(x);
-}
-template <typename M>
-__device__ __forceinline__ M mexp(M x)
-{
-    if constexpr (sizeof(M) == 4) return expf(x); else return exp(x);
+    const float u = __builtin_amdgcn_exp2f((float)(lu * LOG2E));
+    const float x = (float)d;
+    float t = fabsf(x * fmaf(x, fmaf(x, 1.0f / 6.0f, 0.5f), 1.0f));
+    if (x < 0.0f) t = fminf(t, 1.0f);
+    return (double)(u * t);
 }
 
 // Shared memory of one workgroup.
@@ -404,22 +419,22 @@ __device__ __forceinline__ void fast_sweeps(const Inst *__restrict__ I, const Pt
                 j_stop = j;
                 break;
             }
-            double lj[V];
-            bproduct<L, V, M>(pm, pe, sh.c, sh.xw, sh.fm, sh.fe, tid, FastShared<L, V, M>::T, lane, wave, nw, lj);
             double an[V];
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const bool in = p0 + v < N;
-                const double ao = in ? pa[(long)j * N + p0 + v] : -INFINITY;
-                const double lu = in ? plu[(long)j * N + p0 + v] : -INFINITY;
-                an[v] = lu - lj[v];
-                if (lu > -INFINITY) {
-                    if (j < L - 1) est += (double)(mexp<M>((M)lu) * fabs(mexpm1<M>((M)(ao - an[v]))));
-                } else {
-                    an[v] = -INFINITY;
-                }
-                if (in) pa[(long)j * N + p0 + v] = an[v];
-            }
+            double *__restrict__ aj = pa + (long)j * N + p0;
+            const double *__restrict__ luj = plu + (long)j * N + p0;
+            bproduct<L, V, M>(pm, pe, sh.c, sh.xw, sh.fm, sh.fe, tid, FastShared<L, V, M>::T, lane, wave, nw,
+                              [&](int v, double lj) {
+                                  const bool in = p0 + v < N;
+                                  const double lu = in ? luj[v] : -INFINITY;
+                                  double x = lu - lj;
+                                  if (lu > -INFINITY) {
+                                      if (j < L - 1) est += est_term(lu, aj[v] - x);
+                                  } else {
+                                      x = -INFINITY;
+                                  }
+                                  if (in) aj[v] = x;
+                                  an[v] = x;
+                              });
             // new row j into the last slot, then rotate the ring by one
             sp[L - 1] = bf_row<M, V>(an, pm[L - 1], pe[L - 1]);
             M tm[V];
@@ -499,16 +514,13 @@ __device__ __forceinline__ void fast_check(const Inst *__restrict__ I, const Ptr
             wide = true;
             break;
         }
-        double lj[V];
         bproduct<L, V, double>(pm, pe, sh.c, sh.xw, sh.fm, sh.fe, tid, FastShared<L, V, double>::T, lane, wave, nw,
-                               lj);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            if (p0 + v < N) {
-                const double lu = plu[(long)j * N + p0 + v];
-                if (lu > -INFINITY) r += fabs(exp(pa[(long)j * N + p0 + v] + lj[v]) - exp(lu));
-            }
-        }
+                               [&](int v, double lj) {
+                                   if (p0 + v < N) {
+                                       const double lu = plu[(long)j * N + p0 + v];
+                                       if (lu > -INFINITY) r += fabs(exp(pa[(long)j * N + p0 + v] + lj) - exp(lu));
+                                   }
+                               });
         // rotate the ring by one (the rows do not change)
         double tm[V];
 #pragma unroll

@@ -168,7 +168,8 @@ __global__ __launch_bounds__(64) void k_check_all(const Inst *I, Ptrs P, double 
 // have l = L and N <= blockDim.x * V) and, if its state is TS_SWEEP, runs
 // fast_sweeps on it.
 template <int L, int V, typename M>
-__global__ __launch_bounds__(fast_threads(L, sizeof(M) == 4 ? 1 : 0)) void k_fast_sweep(
+__global__ __launch_bounds__(fast_threads(L, sizeof(M) == 4 ? 1 : 0))
+__attribute__((amdgpu_waves_per_eu(fast_waves_per_eu(sizeof(M) == 4 ? 1 : 0)))) void k_fast_sweep(
     const Inst *I, const Ptrs *P, const int *list, int count, RunOpts o, Track *Tr, int *ticket)
 {
     __shared__ FastShared<L, V, M> sh;

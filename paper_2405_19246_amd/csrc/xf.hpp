@@ -93,6 +93,30 @@ __device__ __forceinline__ double xto_log(XF<M> x)
     return fma(e, LN2_HI, fma(e, LN2_LO, xlog_m(x.m)));
 }
 
+// Natural log of m 2^e for an FP32 mantissa m (normal, > 0): the hardware
+// base-2 logarithm of m plus e, times ln 2 in FP64.  Error about an ulp of m,
+// the precision the FP32 products carry anyway.
+__device__ __forceinline__ double xlog_hw(float m, int e)
+{
+    const double t = (double)__builtin_amdgcn_logf(m) + (double)e;
+    return fma(t, LN2_HI, t * LN2_LO);
+}
+
+// exp(a) as an FP32 extended value: a log2(e) split in FP64 into an integer k
+// and a fraction f in [-1/2, 1/2]; 2^f from the hardware base-2 exponential.
+__device__ __forceinline__ XF<float> xfrom_log_hw(double a)
+{
+    if (!(a > -1.0e15)) {
+        if (a != a) return {NAN, 0};
+        return xzero<float>();
+    }
+    if (!(a < 1.0e15)) return {NAN, 0};
+    const double t = a * LOG2E;
+    const double k = rint(t);
+    const float m = __builtin_amdgcn_exp2f((float)(t - k));
+    return {xmant(m), (int)k + xexpo(m)};
+}
+
 template <typename M>
 __device__ __forceinline__ double xto_double(XF<M> x)
 {
@@ -155,7 +179,10 @@ __device__ __forceinline__ int bf_row(const double (&a)[V], M (&m)[V], int &e)
     int hi = XF_ZERO_E, lo = -XF_ZERO_E;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        x[v] = xfrom_log<M>(a[v]);
+        if constexpr (sizeof(M) == 4)
+            x[v] = xfrom_log_hw(a[v]);
+        else
+            x[v] = xfrom_log<M>(a[v]);
         if (x[v].m != M(0)) {
             hi = max(hi, x[v].e);
             lo = min(lo, x[v].e);
@@ -191,11 +218,77 @@ __device__ __forceinline__ double dpp_m(double x)
     const int hi = dpp_i<CTRL, ROWMASK>(0, (int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-// An extended value moved by DPP; lanes without a source get zero.
-template <int CTRL, int ROWMASK = 0xF, typename M>
-__device__ __forceinline__ XF<M> dpp_xf(XF<M> x)
+// Lane-scan element: an extended value with a biased exponent (XF exponent +
+// XB_BIAS, so that the zero value is (0, 0)) and a mantissa left unnormalized
+// between the steps of one scan (each step at most doubles it, so it stays far
+// inside the mantissa type's range).  Lanes without a source lane then read an
+// exact zero from DPP moves with bound_ctrl set.
+constexpr int XB_BIAS = -XF_ZERO_E;
+template <typename M>
+struct XB {
+    M m;
+    int e;
+};
+
+template <typename M>
+__device__ __forceinline__ XB<M> xb_of(XF<M> x)  // x normalized (zero: XF_ZERO_E)
 {
-    return {dpp_m<CTRL, ROWMASK>(x.m), dpp_i<CTRL, ROWMASK>(XF_ZERO_E, x.e)};
+    return {x.m, x.e + XB_BIAS};
+}
+
+template <typename M>
+__device__ __forceinline__ XF<M> xf_of(XB<M> x)
+{
+    if (x.m == M(0)) return xzero<M>();
+    return {xmant(x.m), x.e - XB_BIAS + xexpo(x.m)};
+}
+
+// DPP move with full row and bank masks; lanes without a source read 0.
+template <int CTRL>
+__device__ __forceinline__ int dpp_z(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_z(float x)
+{
+    return __int_as_float(dpp_z<CTRL>(__float_as_int(x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_z(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_z<CTRL>((int)(b & 0xffffffffLL));
+    const int hi = dpp_z<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, typename M>
+__device__ __forceinline__ XB<M> dpp_xb(XB<M> x)
+{
+    return {dpp_z<CTRL>(x.m), dpp_z<CTRL>(x.e)};
+}
+// Row broadcasts (partial row masks: the rows left out read zero).
+template <int CTRL, int ROWMASK, typename M>
+__device__ __forceinline__ XB<M> dpp_xb_rows(XB<M> x)
+{
+    return {dpp_m<CTRL, ROWMASK>(x.m), dpp_i<CTRL, ROWMASK>(0, x.e)};
+}
+
+template <typename M>
+__device__ __forceinline__ XB<M> rlane_xb(XB<M> x, int l)
+{
+    return {rlane(x.m, l), rlane(x.e, l)};
+}
+
+// x + g o: g a discount factor (at most 1, so a zero o keeps an exponent at
+// most 1, below every live value's).
+template <typename M>
+__device__ __forceinline__ XB<M> xb_addg(XB<M> x, XB<M> o, XG<M> g)
+{
+    const M om = fma(o.m, g.hi, o.m * g.lo);
+    const int oe = o.e + g.e;
+    const int e = max(x.e, oe);
+    return {xldexp(x.m, x.e - e) + xldexp(om, oe - e), e};
 }
 
 // Inclusive scan of per-lane aggregates towards higher lanes under the
@@ -203,39 +296,33 @@ __device__ __forceinline__ XF<M> dpp_xf(XF<M> x)
 // 1, 2, 4, 8 inside rows of 16 lanes, then lane 15 of each row to the next row
 // and lane 31 to the upper half.  gstep[s] = g^(V 2^s); glane[s] = g^(V s).
 template <typename M>
-__device__ __forceinline__ XF<M> ks_up_dpp(XF<M> x, const XG<M> *gstep, const XG<M> *glane, int lane)
+__device__ __forceinline__ XB<M> ks_up_dpp(XB<M> x, const XG<M> *gstep, const XG<M> *glane, int lane)
 {
-    x = xadd(x, xmulg(dpp_xf<0x111>(x), gstep[0]));
-    x = xadd(x, xmulg(dpp_xf<0x112>(x), gstep[1]));
-    x = xadd(x, xmulg(dpp_xf<0x114>(x), gstep[2]));
-    x = xadd(x, xmulg(dpp_xf<0x118>(x), gstep[3]));
-    x = xadd(x, xmulg(dpp_xf<0x142, 0xA>(x), glane[(lane & 15) + 1]));
-    x = xadd(x, xmulg(dpp_xf<0x143, 0xC>(x), glane[lane >= 32 ? lane - 31 : 0]));
+    x = xb_addg(x, dpp_xb<0x111>(x), gstep[0]);
+    x = xb_addg(x, dpp_xb<0x112>(x), gstep[1]);
+    x = xb_addg(x, dpp_xb<0x114>(x), gstep[2]);
+    x = xb_addg(x, dpp_xb<0x118>(x), gstep[3]);
+    x = xb_addg(x, dpp_xb_rows<0x142, 0xA>(x), glane[(lane & 15) + 1]);
+    x = xb_addg(x, dpp_xb_rows<0x143, 0xC>(x), glane[lane >= 32 ? lane - 31 : 0]);
     return x;
-}
-
-template <typename M>
-__device__ __forceinline__ XF<M> rlane_xf(XF<M> x, int l)
-{
-    return {rlane(x.m, l), rlane(x.e, l)};
 }
 
 // The same scan towards lower lanes: shifts inside rows of 16 lanes, then the
 // totals from the first lane of rows 1, 2, 3 to the last lane (read as
 // wavefront-uniform values) carried into the rows below.
 template <typename M>
-__device__ __forceinline__ XF<M> ks_down_dpp(XF<M> x, const XG<M> *gstep, const XG<M> *glane, int lane)
+__device__ __forceinline__ XB<M> ks_down_dpp(XB<M> x, const XG<M> *gstep, const XG<M> *glane, int lane)
 {
-    x = xadd(x, xmulg(dpp_xf<0x101>(x), gstep[0]));
-    x = xadd(x, xmulg(dpp_xf<0x102>(x), gstep[1]));
-    x = xadd(x, xmulg(dpp_xf<0x104>(x), gstep[2]));
-    x = xadd(x, xmulg(dpp_xf<0x108>(x), gstep[3]));
-    const XF<M> t3 = rlane_xf(x, 48);
-    const XF<M> t2 = xadd(rlane_xf(x, 32), xmulg(t3, glane[16]));
-    const XF<M> t1 = xadd(rlane_xf(x, 16), xmulg(t2, glane[16]));
+    x = xb_addg(x, dpp_xb<0x101>(x), gstep[0]);
+    x = xb_addg(x, dpp_xb<0x102>(x), gstep[1]);
+    x = xb_addg(x, dpp_xb<0x104>(x), gstep[2]);
+    x = xb_addg(x, dpp_xb<0x108>(x), gstep[3]);
+    const XB<M> t3 = rlane_xb(x, 48);
+    const XB<M> t2 = xb_addg(rlane_xb(x, 32), t3, glane[16]);
+    const XB<M> t1 = xb_addg(rlane_xb(x, 16), t2, glane[16]);
     const int r = lane >> 4;
-    const XF<M> t = r == 0 ? t1 : r == 1 ? t2 : r == 2 ? t3 : xzero<M>();
-    return xadd(x, xmulg(t, glane[16 - (lane & 15)]));
+    const XB<M> t = r == 0 ? t1 : r == 1 ? t2 : r == 2 ? t3 : XB<M>{M(0), 0};
+    return xb_addg(x, t, glane[16 - (lane & 15)]);
 }
 
 
