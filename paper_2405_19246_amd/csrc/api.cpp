@@ -328,6 +328,21 @@ void batch_buffers_free(BatchBuffers *bb)
 //      solve is left sweeping; solves handed to the extended-range solver
 //      mid-way resume there in one more persistent launch;
 //   3. the objective of the fast-path solves, one wavefront each.
+// Predicted sweeps an instance still needs after a warm-up round of `warmup`
+// sweeps: the estimate fell from est_mid to est over the round's second half;
+// assuming the same geometric rate, it reaches tol * f after log(est / (tol f))
+// / rate more sweeps.  Instances not sweeping come last; an estimate that did
+// not fall ranks first.
+static double remaining_sweeps(const Track &T, double tol, int warmup)
+{
+    if (T.state != TS_SWEEP) return -1.0;
+    const double tgt = tol * T.f;
+    if (!(T.est > tgt)) return 0.0;
+    if (!(T.est_mid > T.est) || !(T.est > 0.0)) return INFINITY;
+    const double rate = std::log(T.est_mid / T.est) / (double)(warmup / 2);
+    return std::log(T.est / std::max(tgt, 1e-300)) / rate;
+}
+
 int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const RunOpts &o, hipStream_t s,
                  Result *hR, BatchBuffers *bb, bool timed)
 {
@@ -364,7 +379,7 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
         hT.resize(count);
         for (int i = 0; i < count; ++i) {
             const int64_t itr = hP[i].itr_cap > 0 ? hP[i].itr_cap : o.itr_max;
-            hT[i] = {1.0, INFINITY, INFINITY, 0, itr > 0 ? TS_SWEEP : TS_DONE, 0, 0, 0};
+            hT[i] = {1.0, INFINITY, INFINITY, 0, itr > 0 ? TS_SWEEP : TS_DONE, 0, 0, 0, 0.0};
         }
         HIPCHK(hipMemcpyAsync(bb->dT, hT.data(), sizeof(Track) * count, hipMemcpyHostToDevice, s));
     }
@@ -399,6 +414,14 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
         bool sweeping[MAXL + 1];
         for (int l = 0; l <= MAXL; ++l) sweeping[l] = !group[l].empty();
         std::vector<int64_t> it_before(count, 0);
+        // Longest first: a group larger than the device holds at once starts with
+        // a round of o.warmup sweeps for every instance; from the estimate's decay
+        // over its second half each instance's remaining sweeps are predicted,
+        // and the later rounds take the group in that order, longest first, so
+        // that the slowest solves do not start last.  Iterates are unchanged.
+        bool warm[MAXL + 1];
+        for (int l = 0; l <= MAXL; ++l)
+            warm[l] = o.warmup >= 2 && o.tol >= 0.0 && (int)group[l].size() > FAST_RESIDENT;
         for (;;) {
             bool any = false;
             for (int l = 2; l <= MAXL; ++l) {
@@ -406,8 +429,10 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
                 any = true;
                 const int n = (int)group[l].size();
                 const int cap = 256 * 8;  // persistent workgroups: a few per CU
+                RunOpts so = o;
+                so.budget = warm[l] ? o.warmup : 0;
                 HIPCHK(tbegin(0));
-                HIPCHK(launch_fast(0, l, precision, bb->dI, bb->dP, bb->dorder + goff[l], n, o, bb->dT, bb->dticket,
+                HIPCHK(launch_fast(0, l, precision, bb->dI, bb->dP, bb->dorder + goff[l], n, so, bb->dT, bb->dticket,
                                    std::min(n, cap), fast_waves(l, gmaxN[l], 0, precision), s));
                 HIPCHK(tend());
                 HIPCHK(tbegin(1));
@@ -430,6 +455,16 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
                         handed[i] = 1;
                         resumed.push_back(i);
                     }
+                }
+                if (warm[l]) {
+                    warm[l] = false;
+                    std::vector<int> &g = group[l];
+                    std::vector<double> pr(count, 0.0);
+                    for (int i : g) pr[i] = remaining_sweeps(hT[i], o.tol, o.warmup);
+                    std::stable_sort(g.begin(), g.end(), [&](int x, int y) { return pr[x] > pr[y]; });
+                    std::copy(g.begin(), g.end(), order.begin() + goff[l]);
+                    HIPCHK(hipMemcpyAsync(bb->dorder + goff[l], order.data() + goff[l], sizeof(int) * g.size(),
+                                          hipMemcpyHostToDevice, s));
                 }
             }
         }
@@ -563,7 +598,8 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
     for (int i = 0; i < count; ++i)
         hP[i] = {inst[i].log_u, inst[i].log_phi, nullptr, g_batch.scratch + offs[i], 0, 0,
                  (o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0, 0};
-    RunOpts ro = {o->tol, o->itr_max, o->check_every, (o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0};
+    RunOpts ro = {o->tol, o->itr_max, o->check_every, (o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0, 0,
+                  FAST_WARMUP_SWEEPS};
     BatchBuffers bb = g_batch.bb;
     std::vector<Result> hR(count);
     rc = batch_launch(hI.data(), hP.data(), count, precision, ro, (hipStream_t)hip_stream, hR.data(), &bb, true);

@@ -83,6 +83,7 @@ struct Track {
     int32_t status;   // final status once state is TS_DONE
     int32_t j0;       // TS_ROBUST: marginal at which the extended-range solver resumes
     int32_t checked;  // a residual has been taken
+    double est_mid;   // estimate half-way through a launch with a sweep budget
 };
 constexpr int32_t TS_SWEEP = 0;   // the sweep kernel goes on with it
 constexpr int32_t TS_CHECK = 1;   // a residual check is due
@@ -95,6 +96,8 @@ struct RunOpts {
     int64_t itr_max;      // sweeps in this launch
     int32_t check_every;  // Res every this many sweeps (0: only after the last)
     int32_t flags;
+    int32_t budget;       // register-resident sweeps: pause after this many sweeps of a launch (0: none)
+    int32_t warmup;       // batch host: sweeps of the first round, after which the batch is reordered (0: none)
 };
 
 // Same layout as mmot_result.
@@ -139,6 +142,11 @@ constexpr long fast_capacity(int l, int precision) { return (long)fast_threads(l
 // four wavefronts per compute unit fit its LDS, and the registers then come to
 // 168 per lane (a few values of the outer loops spill).
 constexpr int fast_waves_per_eu(int precision) { return precision == 1 ? 3 : 1; }
+// Batches larger than the workgroups resident at once (three per compute unit)
+// start with a warm-up round of this many sweeps and are then reordered,
+// longest predicted solve first.
+constexpr int FAST_RESIDENT = 768;
+constexpr int FAST_WARMUP_SWEEPS = 256;
 
 // Block floating point holds while the values one thread keeps span at most
 // this many bits: rows of l - 1 marginals (row_spread bits each), v positions

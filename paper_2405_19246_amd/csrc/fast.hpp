@@ -100,6 +100,7 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
 {
     constexpr int n = L - 1;
     constexpr int D = 1 << n;
+    constexpr int NWMAX = fast_threads(L, sizeof(M) == 4 ? 1 : 0) / WAVE;
     const int sl = FWD ? lane : WAVE - 1 - lane;
     const int sw = FWD ? wave : nw - 1 - wave;
 
@@ -166,7 +167,7 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
             }
         }
         // lanes: Kogge-Stone on the thread aggregates (extended range), DPP moves
-        XF<M> excl[D];
+        XB<M> excl[D];
 #pragma unroll
         for (int S = 1; S < D; ++S) {
             if (popc(S) != k) continue;
@@ -174,10 +175,10 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
             XB<M> incl;
             if (FWD) {
                 incl = ks_up_dpp(a, C.gstep[k], C.glane[k], lane);
-                excl[S] = xf_of(dpp_xb<0x138>(incl));  // wave_shr:1, zero in lane 0
+                excl[S] = dpp_xb<0x138>(incl);  // wave_shr:1, zero in lane 0
             } else {
                 incl = ks_down_dpp(a, C.gstep[k], C.glane[k], lane);
-                excl[S] = xf_of(dpp_xb<0x130>(incl));  // wave_shl:1, zero in lane 63
+                excl[S] = dpp_xb<0x130>(incl);  // wave_shl:1, zero in lane 63
             }
             const XF<M> wagg = xf_of(rlane_xb(incl, FWD ? WAVE - 1 : 0));
             if (lane == 0) xw[(half * FAST_MAXW + sw) * D + S] = wagg;
@@ -187,10 +188,15 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
 #pragma unroll
         for (int S = 1; S < D; ++S) {
             if (popc(S) != k) continue;
-            XF<M> wc = xzero<M>();
-            for (int w = 0; w < sw; ++w)  // slots are indexed in scan order
-                wc = xadd(wc, xmulg(xw[(half * FAST_MAXW + w) * D + S], C.gwave[k][sw - 1 - w]));
-            const XF<M> c = xnorm(xadd(excl[S], xmulg(wc, C.glane[k][sl])));
+            // (unrolled to the block's wavefront count, so the LDS reads go out together)
+            XB<M> wc = {M(0), 0};
+#pragma unroll
+            for (int w = 0; w < NWMAX - 1; ++w) {  // slots are indexed in scan order
+                XB<M> o = xb_of(xw[(half * FAST_MAXW + w) * D + S]);
+                if (w >= sw) o = XB<M>{M(0), 0};
+                wc = xb_addg(wc, o, C.gwave[k][max(sw - 1 - w, 0)]);
+            }
+            const XF<M> c = xf_of(xb_addg(excl[S], wc, C.glane[k][sl]));
             cin[S] = c;
             // block exponent of the state: the larger of the local part and the carry part
             const int ec = c.m == M(0) ? XF_ZERO_E : c.e + C.g[k].e;
@@ -372,14 +378,16 @@ __device__ __forceinline__ int decay_bits(const FastConst<M, L, V> &C)
 // residual check is due -- every check_every sweeps if > 0, after the last
 // sweep, or once the estimate est (the marginal errors seen by the updates of
 // one sweep, before each update) falls below tol * f -- and hands the instance
-// to the check kernel.  A product whose values would span too wide an exponent
-// range inside a thread hands it to the extended-range solver instead, which
-// resumes at that marginal.
+// to the check kernel, or until the launch's sweep budget (o.budget, if > 0) is
+// spent.  A product whose values would span too wide an exponent range inside a
+// thread hands it to the extended-range solver instead, which resumes at that
+// marginal.
 template <int L, int V, typename M>
 __device__ __forceinline__ void fast_sweeps(const Inst *__restrict__ I, const Ptrs P, const RunOpts o,
                                             Track *__restrict__ Tr, FastShared<L, V, M> &sh)
 {
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), nw = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
     const long N = I->N;
     const int flags = o.flags | P.flags;
     const long itr_max = P.itr_cap > 0 ? P.itr_cap : o.itr_max;
@@ -405,7 +413,8 @@ __device__ __forceinline__ void fast_sweeps(const Inst *__restrict__ I, const Pt
     for (int s = 0; s < L; ++s) sp[s] = load_row<M, V>(pa + (long)((1 + s) % L) * N, N, p0, pm[s], pe[s]);
 
     int state = TS_DONE, phase = 0, j_stop = 0, status = ST_OK;
-    double est = 0.0;
+    double est = 0.0, est_mid = Tr->est_mid;
+    int done = 0;  // sweeps of this launch
     while (it < itr_max) {
         ++it;
         est = 0.0;
@@ -470,10 +479,21 @@ __device__ __forceinline__ void fast_sweeps(const Inst *__restrict__ I, const Pt
             state = TS_CHECK;
             break;
         }
+        // a sweep budget pauses the instance without a check (the next launch
+        // goes on from the same iterate)
+        ++done;
+        if (o.budget > 0) {
+            if (2 * done == o.budget) est_mid = est;
+            if (done >= o.budget) {
+                state = TS_SWEEP;
+                break;
+            }
+        }
     }
     if (tid == 0) {
         Tr->it = it;
         Tr->est = est;
+        Tr->est_mid = est_mid;
         Tr->state = state;
         Tr->j0 = state == TS_ROBUST ? j_stop : 0;
         if (state == TS_DONE) Tr->status = status;
@@ -487,7 +507,8 @@ template <int L, int V>
 __device__ __forceinline__ void fast_check(const Inst *__restrict__ I, const Ptrs P, const RunOpts o,
                                            Track *__restrict__ Tr, FastShared<L, V, double> &sh)
 {
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), nw = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
     const long N = I->N;
     const long itr_max = P.itr_cap > 0 ? P.itr_cap : o.itr_max;
     const long p0 = (long)tid * V;

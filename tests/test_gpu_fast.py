@@ -141,3 +141,36 @@ def test_fast_hands_over_wide_range_fp32():
         assert r["status"] == 0, r
         err = fastcheck.marginal_errors(d["u"], d["log_phi"].cpu().numpy(), d["h"], d["eps"])
         assert err[:-1].sum() <= 1e-6, err
+
+
+def test_fast_longest_first_reordering_keeps_iterates():
+    # A batch larger than the device holds at once (768 workgroups) starts with
+    # a warm-up round and is then run longest-predicted-first; the pause at the
+    # end of the warm-up round and the new order change no iterate: the same
+    # instances solved in two batches below that size (no warm-up) give
+    # bitwise the same potentials, sweep counts, residuals and objectives.
+    import torch
+    mmot = _mmot()
+    n = 1000
+
+    def make():
+        out = []
+        for s in range(n):
+            u = inputs.marginals(3, 100, K=3, master_seed=31, instance=s)
+            out.append(dict(l=3, N=100, h=inputs.grid_step(100), eps=0.05, u=u))
+        return _dev(out)
+
+    a, b = make(), make()
+    say("batch of %d, reordered after a warm-up round" % n)
+    ra = mmot.solve_batch(a, precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
+    say("same instances in two batches of %d" % (n // 2))
+    rb = mmot.solve_batch(b[: n // 2], precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
+    rb += mmot.solve_batch(b[n // 2:], precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
+    torch.cuda.synchronize()
+    its = [x["iters"] for x in ra]
+    assert max(its) > min(its)  # the order matters for this batch
+    for da, db, x, y in zip(a, b, ra, rb):
+        assert x["status"] == y["status"] == 0
+        assert x["iters"] == y["iters"]
+        assert x["marg_err"] == y["marg_err"] and x["W"] == y["W"]
+        assert torch.equal(da["log_phi"], db["log_phi"])
