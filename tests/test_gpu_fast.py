@@ -144,11 +144,14 @@ def test_fast_hands_over_wide_range_fp32():
 
 
 def test_fast_longest_first_reordering_keeps_iterates():
-    # A batch larger than the device holds at once (768 workgroups) starts with
-    # a warm-up round and is then run longest-predicted-first; the pause at the
-    # end of the warm-up round and the new order change no iterate: the same
+    # A batch larger than the device holds at once (768 workgroups) starts
+    # with a warm-up round of 256 sweeps for every instance, which pauses
+    # without a check; the later rounds take the instances longest-predicted
+    # first.  The pause and the new order change no iterate: the same
     # instances solved in two batches below that size (no warm-up) give
     # bitwise the same potentials, sweep counts, residuals and objectives.
+    # Most of these instances need more than the warm-up (median about 540
+    # sweeps; every seventh, at a smaller eps, thousands), so they pause.
     import torch
     mmot = _mmot()
     n = 1000
@@ -156,19 +159,20 @@ def test_fast_longest_first_reordering_keeps_iterates():
     def make():
         out = []
         for s in range(n):
-            u = inputs.marginals(3, 100, K=3, master_seed=31, instance=s)
-            out.append(dict(l=3, N=100, h=inputs.grid_step(100), eps=0.05, u=u))
+            u = inputs.marginals(3, 200, K=3, master_seed=31, instance=s)
+            out.append(dict(l=3, N=200, h=inputs.grid_step(200), eps=0.004 if s % 7 == 0 else 0.01, u=u))
         return _dev(out)
 
     a, b = make(), make()
-    say("batch of %d, reordered after a warm-up round" % n)
+    say("batch of %d with a warm-up round and reordering" % n)
     ra = mmot.solve_batch(a, precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
     say("same instances in two batches of %d" % (n // 2))
     rb = mmot.solve_batch(b[: n // 2], precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
     rb += mmot.solve_batch(b[n // 2:], precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
     torch.cuda.synchronize()
-    its = [x["iters"] for x in ra]
-    assert max(its) > min(its)  # the order matters for this batch
+    its = np.array([x["iters"] for x in ra])
+    print("sweeps: min %d median %d max %d" % (its.min(), np.median(its), its.max()))
+    assert (its > 256).mean() > 0.75 and its.max() > 5 * 256
     for da, db, x, y in zip(a, b, ra, rb):
         assert x["status"] == y["status"] == 0
         assert x["iters"] == y["iters"]
