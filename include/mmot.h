@@ -156,13 +156,23 @@ typedef struct {
 } mmot_instance;
 
 /*
- * Solve `count` independent instances of mixed l, N, eps in ONE persistent
- * launch: each wavefront takes the next unsolved instance (largest estimated
- * work first) until none is left, and runs its whole solve (sweeps, FP64
- * checks every o->check_every sweeps, FP64 objective).  precision as in
- * mmot_problem.  res: host [count], written after synchronising hip_stream.
- * Returns MMOT_OK if every instance converged, MMOT_NOT_CONVERGED if some hit
- * itr_max, MMOT_ERR_NUMERIC if some failed; per-instance status is in res.
+ * Solve `count` independent instances of mixed l, N, eps.  Instances whose N
+ * fits one workgroup (l <= 4, N <= 1024) run on the register-resident path:
+ * rounds of a sweep kernel (one workgroup per instance, until the stopping
+ * estimate asks for a check) and an FP64 check kernel.  All others run in one
+ * persistent launch of the extended-range solver, one wavefront per instance
+ * taking the next unsolved one (largest estimated work first) until none is
+ * left.  When one l has more register-resident instances than the device
+ * holds at once (768), the first round gives each of them 256 sweeps and
+ * pauses (no check); the later rounds take them longest-predicted first (from
+ * the estimate's decay over sweeps 128..256), so that the slowest solves
+ * start early.  None of this changes an instance's iterates: they are those
+ * of solving it alone.  Stopping as in mmot_solve (FP64 residual, estimate-
+ * triggered or every o->check_every sweeps, and after the last), then the FP64
+ * objective.  precision as in mmot_problem.  res: host [count], written after
+ * synchronising hip_stream.  Returns MMOT_OK if every instance converged,
+ * MMOT_NOT_CONVERGED if some hit itr_max, MMOT_ERR_NUMERIC if some failed;
+ * per-instance status is in res.
  */
 int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_t precision, const mmot_opts *o,
                      void *hip_stream, mmot_result *res);
