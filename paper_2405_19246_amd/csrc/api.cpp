@@ -359,9 +359,6 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
         else robust.push_back(i);
     }
     by_cost(robust);
-    // the robust list runs as [l <= 6 | l = 7 | l = 8], each part largest estimated work first
-    std::stable_sort(robust.begin(), robust.end(),
-                     [&](int x, int y) { return std::max(hI[x].l, 6) < std::max(hI[y].l, 6); });
     // dorder: [robust | group 2 | group 3 | ...], then the second half for resumed and objective lists
     std::vector<int> order;
     order.reserve(2 * (size_t)count);
@@ -405,26 +402,11 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     auto tbegin = [&](int kind) { return tmon ? tm.begin(kind, s, &slot) : hipSuccess; };
     auto tend = [&]() { return tmon ? tm.end(slot, s) : hipSuccess; };
     if (!robust.empty()) {
-        // l <= 6 in one launch of the mixed-l kernel; l = 7 and 8 (heavier per
-        // wavefront, see k_solve_batch_l) each in a launch of their own
-        int off = 0;
-        for (int l = 2; l <= MAXL;) {
-            int e = off;
-            while (e < (int)robust.size() && (hI[robust[e]].l <= 6 ? l <= 6 : hI[robust[e]].l == l)) ++e;
-            const int n = e - off;
-            if (n > 0) {
-                HIPCHK(tbegin(2));
-                if (l <= 6)
-                    HIPCHK(launch_solve_batch(precision, bb->dI, bb->dP, bb->dorder + off, n, o, bb->dR, bb->dticket,
-                                              std::max(1, std::min((n + 3) / 4, 4096)), s));
-                else
-                    HIPCHK(launch_solve_batch_l(l, precision, bb->dI, bb->dP, bb->dorder + off, n, o, bb->dR,
-                                                bb->dticket, std::max(1, std::min(n, 4096)), s));
-                HIPCHK(tend());
-            }
-            off = e;
-            l = l <= 6 ? 7 : l + 1;
-        }
+        const int n = (int)robust.size();
+        const int blocks = std::max(1, std::min((n + 3) / 4, 4096));
+        HIPCHK(tbegin(2));
+        HIPCHK(launch_solve_batch(precision, bb->dI, bb->dP, bb->dorder, n, o, bb->dR, bb->dticket, blocks, s));
+        HIPCHK(tend());
     }
     std::vector<int> resumed, objective;
     std::vector<char> handed(count, 0);  // handed to the extended-range solver

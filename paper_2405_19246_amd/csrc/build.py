@@ -20,7 +20,7 @@ ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 OUT = os.path.join(PKG, "libmmot.so")
 ARCH = os.environ.get("MMOT_OFFLOAD_ARCH", "gfx950")
-LMAX = 8
+LMAX = 6
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

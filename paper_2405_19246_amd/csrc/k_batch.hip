@@ -47,8 +47,6 @@ hipError_t launch_solve_batch(int precision, const Inst *dI, const Ptrs *dP, con
         case 4: return fn##4(__VA_ARGS__);          \
         case 5: return fn##5(__VA_ARGS__);          \
         case 6: return fn##6(__VA_ARGS__);          \
-        case 7: return fn##7(__VA_ARGS__);          \
-        case 8: return fn##8(__VA_ARGS__);          \
         default: return hipErrorInvalidValue;       \
     }
 
@@ -57,13 +55,6 @@ hipError_t launch_fast(int kind, int l, int precision, const Inst *dI, const Ptr
 {
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, dticket, 0);
     MMOT_DISPATCH(launch_fast_l, l, kind, precision, dI, dP, dlist, count, o, dT, dticket, blocks, waves, s)
-}
-
-hipError_t launch_solve_batch_l(int l, int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,
-                                const RunOpts &o, Result *dR, int *dticket, int blocks, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, dticket, 0);
-    MMOT_DISPATCH(launch_batch_l, l, precision, dI, dP, dorder, count, o, dR, dticket, blocks, s)
 }
 
 hipError_t launch_objective_batch(const Inst *dI, const Ptrs *dP, const int *dlist, int count, Result *dR,

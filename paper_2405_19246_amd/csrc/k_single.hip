@@ -78,19 +78,6 @@ hipError_t MMOT_CAT(launch_single_l, MMOT_L)(int precision, const Inst *dI, cons
     return launch_single_t<MMOT_L>(precision, dI, P, o, dR, s);
 }
 
-hipError_t MMOT_CAT(launch_batch_l, MMOT_L)(int precision, const Inst *dI, const Ptrs *dP, const int *dorder,
-                                             int count, const RunOpts &o, Result *dR, int *dticket, int blocks,
-                                             hipStream_t s)
-{
-    if (precision == 1)
-        hipLaunchKernelGGL((k_solve_batch_l<MMOT_L, float>), dim3(blocks), dim3(WAVE), 0, s, dI, dP, dorder, count, o,
-                           dR, dticket);
-    else
-        hipLaunchKernelGGL((k_solve_batch_l<MMOT_L, double>), dim3(blocks), dim3(WAVE), 0, s, dI, dP, dorder, count,
-                           o, dR, dticket);
-    return hipGetLastError();
-}
-
 hipError_t MMOT_CAT(launch_fast_l, MMOT_L)(int kind, int precision, const Inst *dI, const Ptrs *dP,
                                             const int *dlist, int count, const RunOpts &o, Track *dT, int *dticket,
                                             int blocks, int waves, hipStream_t s)

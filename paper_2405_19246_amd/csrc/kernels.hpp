@@ -102,7 +102,13 @@ __device__ void solve_dispatch(const Inst *I, const Ptrs P, const RunOpts o, Res
         case 4: solve_one<4, M>(I, P, o, R, lane); break;
         case 5: solve_one<5, M>(I, P, o, R, lane); break;
         case 6: solve_one<6, M>(I, P, o, R, lane); break;
-        default: break;  // l > 6: k_solve_batch_l
+#if MMOT_BUILD_MAXL >= 7
+        case 7: solve_one<7, M>(I, P, o, R, lane); break;
+#endif
+#if MMOT_BUILD_MAXL >= 8
+        case 8: solve_one<8, M>(I, P, o, R, lane); break;
+#endif
+        default: break;
     }
 }
 
@@ -132,22 +138,6 @@ __global__ __launch_bounds__(256, 2) void k_solve_batch(const Inst *I, const Ptr
     }
 }
 
-
-// Persistent batch of one l.  Used for l > 6, whose solve keeps too many
-// states per lane to share a kernel (registers, scratch) with the smaller l;
-// one wavefront per workgroup.
-template <int L, typename M>
-__global__ __launch_bounds__(64) void k_solve_batch_l(const Inst *I, const Ptrs *P, const int *order, int count,
-                                                      RunOpts o, Result *R, int *ticket)
-{
-    const int lane = threadIdx.x & (WAVE - 1);
-    for (;;) {
-        const int t = wave_ticket(ticket, lane);
-        if (t >= count) break;
-        const int idx = __builtin_amdgcn_readfirstlane(order[t]);
-        solve_one<L, M>(&I[idx], P[idx], o, &R[idx], lane);
-    }
-}
 
 template <int L, int V, typename E, int MODE>
 __global__ __launch_bounds__(64) void k_pass(const Inst *I, Ptrs P, int j, double *result)

@@ -5,7 +5,7 @@
 #include "common.hpp"
 
 #ifndef MMOT_BUILD_MAXL
-#define MMOT_BUILD_MAXL 8
+#define MMOT_BUILD_MAXL 6
 #endif
 
 namespace mmot {
@@ -24,22 +24,13 @@ hipError_t launch_solve_single(int l, int precision, const Inst *dI, const Ptrs 
                                   hipStream_t s);                                                        \
     hipError_t launch_fast_l##l(int kind, int precision, const Inst *dI, const Ptrs *dP, const int *dlist,    \
                                 int count, const RunOpts &o, Track *dT, int *dticket, int blocks, int waves,   \
-                                hipStream_t s);                                                        \
-    hipError_t launch_batch_l##l(int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,  \
-                                 const RunOpts &o, Result *dR, int *dticket, int blocks, hipStream_t s);
+                                hipStream_t s);
 MMOT_DECL_L(2)
 MMOT_DECL_L(3)
 MMOT_DECL_L(4)
 MMOT_DECL_L(5)
 MMOT_DECL_L(6)
-MMOT_DECL_L(7)
-MMOT_DECL_L(8)
 #undef MMOT_DECL_L
-
-// Persistent solve of `count` listed instances that all have this l (l = 7, 8:
-// one wavefront per workgroup, k_solve_batch_l).  Resets *dticket first.
-hipError_t launch_solve_batch_l(int l, int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,
-                                const RunOpts &o, Result *dR, int *dticket, int blocks, hipStream_t s);
 
 // Fast path over a list of instances that all have l and N <= waves * 64 * V:
 // kind 0 runs the sweeps (V = fast_v(l, precision)), kind 1 the FP64 residual

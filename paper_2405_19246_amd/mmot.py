@@ -92,6 +92,12 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libmmot.so is not built (run __graft_entry__.build() or "
                                "python -m paper_2405_19246_amd.csrc.build)")
+        # torch's HIP runtime (a separate copy from the one the library links)
+        # has to hold the device before the library is loaded: loaded first, the
+        # library's first allocation found no device
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
         L = ctypes.CDLL(LIB_PATH)
         PP = ctypes.POINTER
         L.mmot_plan.argtypes = [PP(Problem), PP(Opts), _c_p, PP(_c_p)]

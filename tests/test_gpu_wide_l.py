@@ -12,7 +12,14 @@ from gpu_util import log_rel_err, potentials_err, say, to_dev
 from oracle import fastcheck
 from paper_2405_19246_amd import inputs
 
-pytestmark = pytest.mark.gpu
+# Switched off: in the first GPU run of an l = 7 build, the FP64 product at
+# l = 7, N = 5 (one chunk) passed and the one at N = 70 (two chunks, the
+# forward-checkpoint path) left the GPU faulted.  The same case emulated on the
+# CPU, with AddressSanitizer, is clean and matches the oracle to 2e-14, and no
+# cause has been found in the code, so l > 6 returns MMOT_ERR_UNSUPPORTED again
+# and these tests stay skipped until a cause is shown.
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="l = 7, 8 switched off: GPU fault at l=7 N=70 (two chunks), cause not found")]
 
 FP64_TOL = 1e-12
 WIDE = [(7, 5), (7, 70), (8, 3), (8, 65)]
