@@ -227,3 +227,21 @@ def test_zero_marginal_entries():
     assert np.all(np.isneginf(got[1, :5]))
     assert potentials_err(got, ref["log_phi"]) < FP64_TOL
     assert abs(res["W"] - ref["W"]) < FP64_TOL * abs(ref["W"])
+
+
+def test_plain_method_ten_seeds_batched_fp64():
+    # The small FP64 configuration with its ten seeds in one batch: l = 3,
+    # N = 64, eps = 0.1, exactly 500 sweeps each, against the O(N) C checker
+    # (pinned to the dense oracle, which the test above uses on two seeds).
+    mmot = _mmot()
+    insts = []
+    for s in range(10):
+        u, h, eps = inputs.workload("l3_n64_eps0.1", instance=s)
+        insts.append(dict(l=3, N=64, h=h, eps=eps, u=u, log_u=to_dev(np.log(u)), log_phi=to_dev(np.zeros((3, 64)))))
+    say("batch fp64 l=3 N=64, 10 seeds, 500 sweeps")
+    res = mmot.solve_batch(insts, precision=mmot.FP64, tol=-1.0, itr_max=500, check_every=0)
+    for d, r in zip(insts, res):
+        ref = fastcheck.sinkhorn(d["u"], d["h"], d["eps"], itmax=500, check_every=500)
+        assert r["iters"] == 500 and r["status"] == 0
+        assert potentials_err(d["log_phi"].cpu().numpy(), ref["log_phi"]) < FP64_TOL
+        assert abs(r["W"] - ref["W"]) < FP64_TOL * abs(ref["W"])
