@@ -47,7 +47,7 @@ extern "C" {
 #define MMOT_ERR_HIP (-6)         /* a HIP runtime call failed (message names it) */
 #define MMOT_ERR_STATE (-7)       /* server stopped, unknown ticket, or call out of order */
 
-#define MMOT_MAX_L 8              /* largest number of marginals per problem */
+#define MMOT_MAX_L 10             /* largest number of marginals per problem */
 
 #define MMOT_FP64 0
 #define MMOT_FP32 1

@@ -353,16 +353,24 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     auto by_cost = [&](std::vector<int> &v) {
         std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     };
-    std::vector<int> robust, group[MAXL + 1];
+    std::vector<int> robust, group[MAXL + 1], wide[MAXL + 1];
     for (int i = 0; i < count; ++i) {
-        if (!(flags & F_NO_FAST) && fast_eligible(hI[i], precision)) group[hI[i].l].push_back(i);
+        if (hI[i].l >= WIDE_MINL) wide[hI[i].l].push_back(i);
+        else if (!(flags & F_NO_FAST) && fast_eligible(hI[i], precision)) group[hI[i].l].push_back(i);
         else robust.push_back(i);
     }
     by_cost(robust);
-    // dorder: [robust | group 2 | group 3 | ...], then the second half for resumed and objective lists
+    // dorder: [robust | wide 7 | wide 8 | ... | group 2 | group 3 | ...], then the second half for
+    // resumed and objective lists
     std::vector<int> order;
     order.reserve(2 * (size_t)count);
     order.insert(order.end(), robust.begin(), robust.end());
+    int woff[MAXL + 1] = {0};
+    for (int l = WIDE_MINL; l <= MAXL; ++l) {
+        by_cost(wide[l]);
+        woff[l] = (int)order.size();
+        order.insert(order.end(), wide[l].begin(), wide[l].end());
+    }
     int goff[MAXL + 1] = {0}, gmaxN[MAXL + 1] = {0};
     for (int l = 2; l <= MAXL; ++l) {
         by_cost(group[l]);
@@ -373,7 +381,9 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     HIPCHK(hipMemcpyAsync(bb->dI, hI, sizeof(Inst) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(bb->dP, hP, sizeof(Ptrs) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(bb->dorder, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
-    const bool any_fast = (int)robust.size() < count;
+    size_t nwide = 0;
+    for (int l = WIDE_MINL; l <= MAXL; ++l) nwide += wide[l].size();
+    const bool any_fast = robust.size() + nwide < (size_t)count;
     std::vector<Track> hT;
     if (any_fast) {
         hT.resize(count);
@@ -406,6 +416,13 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
         const int blocks = std::max(1, std::min((n + 3) / 4, 4096));
         HIPCHK(tbegin(2));
         HIPCHK(launch_solve_batch(precision, bb->dI, bb->dP, bb->dorder, n, o, bb->dR, bb->dticket, blocks, s));
+        HIPCHK(tend());
+    }
+    for (int l = WIDE_MINL; l <= MAXL; ++l) {
+        if (wide[l].empty()) continue;
+        HIPCHK(tbegin(2));
+        HIPCHK(launch_wide_batch(l, precision, bb->dI, bb->dP, bb->dorder + woff[l], (int)wide[l].size(), o, bb->dR,
+                                 bb->dticket, s));
         HIPCHK(tend());
     }
     std::vector<int> resumed, objective;

@@ -20,7 +20,8 @@ ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 OUT = os.path.join(PKG, "libmmot.so")
 ARCH = os.environ.get("MMOT_OFFLOAD_ARCH", "gfx950")
-LMAX = 6
+LMAX = 6   # the one-wavefront and register-resident kernels
+WMAX = 10  # the team-layout kernels (l = 7 .. WMAX)
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,11 +39,24 @@ def _units():
     units = []
     for l in range(2, LMAX + 1):
         units.append((os.path.join(HERE, "k_single.hip"), "k_single_l%d.o" % l, ["-DMMOT_L=%d" % l]))
+    for l in range(7, WMAX + 1):
+        units.append((os.path.join(HERE, "k_wide.hip"), "k_wide_l%d.o" % l, ["-DMMOT_L=%d" % l]))
     units.append((os.path.join(HERE, "k_batch.hip"), "k_batch.o", []))
     units.append((os.path.join(HERE, "api.cpp"), "api.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "serve.cpp"), "serve.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "tables.cpp"), "tables.o", []))
     return units
+
+
+def _stale(obj: str) -> bool:
+    """True if obj is missing or older than any source or header of the library."""
+    path = os.path.join(BUILD, obj)
+    if not os.path.exists(path):
+        return True
+    t = os.path.getmtime(path)
+    srcs = [os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith((".hpp", ".hip", ".cpp"))]
+    srcs.append(os.path.join(ROOT, "include", "mmot.h"))
+    return any(os.path.getmtime(f) > t for f in srcs)
 
 
 def _compile(args):
@@ -55,12 +69,18 @@ def _compile(args):
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def build(jobs: int | None = None, verbose: bool = True, only_stale: bool = False) -> str:
+    """Compile every unit (only_stale: only units older than a source) and link libmmot.so."""
     os.makedirs(BUILD, exist_ok=True)
     units = _units()
-    jobs = jobs or min(len(units), max(1, (os.cpu_count() or 4)))
+    if only_stale:
+        keep = [u for u in units if not _stale(u[1])]
+        units = [u for u in units if _stale(u[1])]
+    else:
+        keep = []
+    jobs = jobs or max(1, min(len(units), os.cpu_count() or 4))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, units))
+        objs = list(ex.map(_compile, units)) + [u[1] for u in keep]
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + \
           [os.path.join(BUILD, o) for o in objs] + ["-lpthread"]
@@ -74,5 +94,5 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(only_stale="--stale" in sys.argv)
     sys.exit(0)

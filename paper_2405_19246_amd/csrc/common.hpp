@@ -4,7 +4,7 @@
 
 namespace mmot {
 
-constexpr int MAXL = 8;   // largest number of marginals (MMOT_MAX_L)
+constexpr int MAXL = 10;  // largest number of marginals (MMOT_MAX_L)
 constexpr int MAXV = 8;   // largest number of grid positions one lane owns per chunk
 constexpr int WAVE = 64;  // CDNA wavefront width
 
@@ -159,5 +159,35 @@ constexpr bool bf_fits_range(int precision, int l, int v, int row_spread, int de
 
 // Bytes of one scan element of each kind (for checkpoint storage).
 constexpr int elem_bytes(int kind) { return kind == 0 ? 8 : kind == 2 ? 32 : 16; }
+
+// Team layout of the subset-state solver (wide.hpp) for l marginals: the
+// 2^(l-1) states of a position are spread over TL lanes and RG registers per
+// lane.  Element kinds: words = live 32-bit registers of one element (FP32
+// extended value 2, FP64 3, FP64 value + cost-weighted value 6), bytes = its
+// size in memory.
+constexpr int WIDE_MINL = 7;   // l from which batches and plans use the team layout
+constexpr int WIDE_MAXL = 10;  // largest l the team layout is built for
+constexpr int wide_states(int l) { return 1 << (l - 1); }
+constexpr int wide_tl(int l) { return wide_states(l) < WAVE ? wide_states(l) : WAVE; }
+constexpr int wide_rg(int l) { return wide_states(l) / wide_tl(l); }
+// positions per recompute block: about 48 registers of forward states per lane
+constexpr int wide_ck(int l, int words)
+{
+    return 48 / (wide_rg(l) * words) < 1 ? 1 : (48 / (wide_rg(l) * words) > 16 ? 16 : 48 / (wide_rg(l) * words));
+}
+// checkpoint bytes of one pass over len positions
+constexpr long wide_ck_bytes(int l, int words, int bytes, long len)
+{
+    return ((len + wide_ck(l, words) - 1) / wide_ck(l, words)) * (long)wide_states(l) * (long)bytes;
+}
+// checkpoint bytes of one instance: the largest over the FP32, FP64 and objective passes
+constexpr long wide_scratch_bytes(int l, long N)
+{
+    return wide_ck_bytes(l, 2, 8, N) > wide_ck_bytes(l, 3, 16, N)
+               ? (wide_ck_bytes(l, 2, 8, N) > wide_ck_bytes(l, 6, 32, N) ? wide_ck_bytes(l, 2, 8, N)
+                                                                         : wide_ck_bytes(l, 6, 32, N))
+               : (wide_ck_bytes(l, 3, 16, N) > wide_ck_bytes(l, 6, 32, N) ? wide_ck_bytes(l, 3, 16, N)
+                                                                          : wide_ck_bytes(l, 6, 32, N));
+}
 
 }  // namespace mmot

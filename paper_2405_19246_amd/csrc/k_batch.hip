@@ -69,7 +69,27 @@ hipError_t launch_objective_batch(const Inst *dI, const Ptrs *dP, const int *dli
 hipError_t launch_pass(int l, int precision, int mode, const Inst *dI, const Ptrs &P, int j, double *dres,
                        hipStream_t s)
 {
+    switch (l) {
+        case 7: return launch_wide_pass_l7(precision, mode, dI, P, j, dres, s);
+        case 8: return launch_wide_pass_l8(precision, mode, dI, P, j, dres, s);
+        case 9: return launch_wide_pass_l9(precision, mode, dI, P, j, dres, s);
+        case 10: return launch_wide_pass_l10(precision, mode, dI, P, j, dres, s);
+        default: break;
+    }
     MMOT_DISPATCH(launch_pass_l, l, precision, mode, dI, P, j, dres, s)
+}
+
+hipError_t launch_wide_batch(int l, int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,
+                             const RunOpts &o, Result *dR, int *dticket, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, dticket, 0);
+    switch (l) {
+        case 7: return launch_wide_batch_l7(precision, dI, dP, dorder, count, o, dR, dticket, s);
+        case 8: return launch_wide_batch_l8(precision, dI, dP, dorder, count, o, dR, dticket, s);
+        case 9: return launch_wide_batch_l9(precision, dI, dP, dorder, count, o, dR, dticket, s);
+        case 10: return launch_wide_batch_l10(precision, dI, dP, dorder, count, o, dR, dticket, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_solve_single(int l, int precision, const Inst *dI, const Ptrs &P, const RunOpts &o, Result *dR,

@@ -5,7 +5,7 @@
 #include "common.hpp"
 
 #ifndef MMOT_BUILD_MAXL
-#define MMOT_BUILD_MAXL 6
+#define MMOT_BUILD_MAXL 10
 #endif
 
 namespace mmot {
@@ -31,6 +31,23 @@ MMOT_DECL_L(4)
 MMOT_DECL_L(5)
 MMOT_DECL_L(6)
 #undef MMOT_DECL_L
+
+// Team-layout kernels (wide.hpp), l = WIDE_MINL .. WIDE_MAXL.
+#define MMOT_DECL_W(l)                                                                                      \
+    hipError_t launch_wide_pass_l##l(int precision, int mode, const Inst *dI, const Ptrs &P, int j, double *dres, \
+                                     hipStream_t s);                                                        \
+    hipError_t launch_wide_batch_l##l(int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count, \
+                                      const RunOpts &o, Result *dR, int *dticket, hipStream_t s);
+MMOT_DECL_W(7)
+MMOT_DECL_W(8)
+MMOT_DECL_W(9)
+MMOT_DECL_W(10)
+#undef MMOT_DECL_W
+
+// Persistent batch of instances that all have l (>= WIDE_MINL): one team of
+// lanes per instance, whole solves.  Resets *dticket first.
+hipError_t launch_wide_batch(int l, int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,
+                             const RunOpts &o, Result *dR, int *dticket, hipStream_t s);
 
 // Fast path over a list of instances that all have l and N <= waves * 64 * V:
 // kind 0 runs the sweeps (V = fast_v(l, precision)), kind 1 the FP64 residual

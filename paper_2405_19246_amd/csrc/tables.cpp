@@ -66,6 +66,7 @@ Inst make_inst(int l, int64_t N, double h, double eps)
 // Checkpoint bytes for one instance: the largest over the passes it runs.
 size_t scratch_bytes(int l, int64_t N, int precision)
 {
+    if (l >= WIDE_MINL) return ((size_t)wide_scratch_bytes(l, (long)N) + 255) & ~(size_t)255;
     const int D1 = (1 << (l - 1)) - 1;
     size_t best = 0;
     const int kinds[3] = {precision == MMOT_FP32 ? 0 : 1, 2, 3};

@@ -1,0 +1,513 @@
+// The O(N) tensor-vector product with the subset states spread over the lanes.
+//
+// Same dynamic program as scan.hpp (gap form of the L1 cost, Sec. 4.2 with the
+// ordering classes merged into subsets), laid out for many marginals: the 2^(l-1)
+// states of one position live across the lanes of a team and a few registers per
+// lane, and positions are walked one after the other.  Per position a state S of
+// the l - 1 summed marginals R takes
+//     A(S) <- g(|S|) A(S)                       (the gap before the position)
+//     A(S) <- A(S) + A(S \ r) phi_r(x)         for each item r in S, one item at a time
+// (the item-by-item form of placing any subset of R at x: l 2^(l-2) multiply-adds
+// per position instead of the 3^(l-1) of a sum over all placed subsets), so no
+// lane keeps more than a handful of states and nothing spills.
+//
+// Layout.  State index S = i * TL + t: the low LB = log2(TL) bits of S (items
+// 0..LB-1) are the lane t inside the team, the high bits (items LB..l-2) the
+// register i.  An item step over a lane bit reads the partner state from the lane
+// 2^b below (DPP row shift inside rows of 16 lanes, a swizzle for 16, a permute
+// for 32); over a register bit it stays in the lane.  Backward states are held
+// complemented: the lane and register of forward state S hold the backward state
+// of R \ S, so the backward item step reads the lane 2^b above and the combine
+//     J_j(y) = sum_S F_y(S) g(|R \ S|) B_{y+1}(R \ S)
+// is a per-lane product followed by one team-wide sum.
+//
+// The combine needs F_y and B_{y+1} together.  The forward walk stores its state
+// every CK positions (checkpoints in scratch memory); the backward walk takes the
+// blocks last to first, recomputes each block's CK forward states from its
+// checkpoint into registers and combines while it steps backwards.  Every value
+// is an extended-range number (XF: mantissa and exact integer power-of-two
+// exponent), as in the one-wavefront solver, so no potential size over- or
+// underflows.
+#pragma once
+#include <type_traits>
+
+#include "scan.hpp"
+
+namespace mmot {
+
+__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+// Registers an element of a scan occupies (mantissa + exponent).
+template <typename E>
+struct EWords;
+template <>
+struct EWords<XF<float>> {
+    static constexpr int n = 2;
+};
+template <>
+struct EWords<XF<double>> {
+    static constexpr int n = 3;
+};
+template <>
+struct EWords<DXF> {
+    static constexpr int n = 6;
+};
+
+// Team layout of the states of an l-marginal product in element type E.
+template <int L, typename E>
+struct WL {
+    static constexpr int n = L - 1;               // summed marginals
+    static constexpr int D = wide_states(L);      // states (subsets of R)
+    static constexpr int TL = wide_tl(L);         // lanes per team
+    static constexpr int TPW = WAVE / TL;         // teams per wavefront
+    static constexpr int RG = wide_rg(L);         // states per lane
+    static constexpr int LB = ilog2c(TL);         // items held across lanes
+    static constexpr int RB = ilog2c(RG);         // items held across registers
+    static constexpr int CK = wide_ck(L, EWords<E>::n);  // positions per recompute block
+};
+
+// ---- lane moves inside a team ---------------------------------------------------
+// UP = false: the value of lane t - 2^B; UP = true: of lane t + 2^B.  Only lanes
+// whose source lies in the same team use the result.
+template <int B, bool UP>
+__device__ __forceinline__ int lmove(int x)
+{
+    if constexpr (B < 4) {
+        return __builtin_amdgcn_update_dpp(0, x, UP ? (0x100 + (1 << B)) : (0x110 + (1 << B)), 0xF, 0xF, true);
+    } else if constexpr (B == 4) {
+        return __builtin_amdgcn_ds_swizzle(x, 0x401F);  // lane ^ 16 inside 32 lanes
+    } else {
+        return __builtin_amdgcn_ds_bpermute((int)(((threadIdx.x & 63) ^ 32) << 2), x);
+    }
+}
+template <int B, bool UP>
+__device__ __forceinline__ float lmove(float x)
+{
+    return __int_as_float(lmove<B, UP>(__float_as_int(x)));
+}
+template <int B, bool UP>
+__device__ __forceinline__ double lmove(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = lmove<B, UP>((int)(b & 0xffffffffLL));
+    const int hi = lmove<B, UP>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int B, bool UP, typename M>
+__device__ __forceinline__ XF<M> lmove(XF<M> x)
+{
+    return {lmove<B, UP>(x.m), lmove<B, UP>(x.e)};
+}
+template <int B, bool UP>
+__device__ __forceinline__ DXF lmove(DXF x)
+{
+    return {lmove<B, UP>(x.v), lmove<B, UP>(x.w)};
+}
+
+// c ? a : b field by field (a select of whole structs can become a per-lane
+// choice between two private-memory addresses).
+template <typename M>
+__device__ __forceinline__ XF<M> esel(bool c, XF<M> a, XF<M> b)
+{
+    return {c ? a.m : b.m, c ? a.e : b.e};
+}
+__device__ __forceinline__ DXF esel(bool c, DXF a, DXF b) { return {esel(c, a.v, b.v), esel(c, a.w, b.w)}; }
+
+// Wavefront-local ordering of LDS and global accesses between the lanes of a
+// team (one team never spans more than a wavefront).
+__device__ __forceinline__ void team_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Per-lane constants of one walk: g(level) for the levels this lane's registers
+// can hold.  Forward state S_i = i TL + t has level m + |t| + |i|; the
+// complemented backward state has level m + n - |t| - |i|.
+template <int L, typename E>
+struct WConst {
+    using M = typename ET<E>::MT;
+    static constexpr int RB = WL<L, E>::RB;
+    XG<M> g[RB + 1];
+    double pc[RB + 1];  // level (l - level): weight of a gap for the objective
+};
+
+template <int L, typename E>
+__device__ __forceinline__ WConst<L, E> wconst(double hoe, int base, int sign)
+{
+    using M = typename ET<E>::MT;
+    WConst<L, E> c;
+#pragma unroll
+    for (int k = 0; k <= WL<L, E>::RB; ++k) {
+        const int lev = base + sign * k;
+        const bool ok = lev >= 0 && lev <= L;
+        c.g[k] = ok ? xg_from_log<M>(-(double)(lev * (L - lev)) * hoe) : XG<M>{M(0), M(0), XF_ZERO_E, 0};
+        c.pc[k] = ok ? (double)(lev * (L - lev)) : 0.0;
+    }
+    return c;
+}
+
+// One position of a walk: the gap factor, then the items placed at the position.
+// ph[r] is phi of item r at the position.  BWD: complemented backward states.
+template <int L, typename E, bool BWD, int RG_ = WL<L, E>::RG>
+__device__ __forceinline__ void wstep(E (&A)[RG_], const XF<typename ET<E>::MT> *ph, const WConst<L, E> &c, int t)
+{
+    using W = WL<L, E>;
+    using T_ = ET<E>;
+#pragma unroll
+    for (int i = 0; i < W::RG; ++i) A[i] = T_::disc(A[i], c.g[popc(i)], c.pc[popc(i)]);
+    // items across lanes
+#pragma unroll
+    for (int r = 0; r < W::LB; ++r) {
+        const XF<typename T_::MT> p = ph[r];
+        const bool upd = BWD ? !((t >> r) & 1) : ((t >> r) & 1);
+#pragma unroll
+        for (int i = 0; i < W::RG; ++i) {
+            const E o = (r == 0)   ? lmove<0, BWD>(A[i])
+                        : (r == 1) ? lmove<1, BWD>(A[i])
+                        : (r == 2) ? lmove<2, BWD>(A[i])
+                        : (r == 3) ? lmove<3, BWD>(A[i])
+                        : (r == 4) ? lmove<4, BWD>(A[i])
+                                   : lmove<5, BWD>(A[i]);
+            const E nv = T_::add(A[i], T_::scale(o, p));
+            A[i] = esel(upd, nv, A[i]);
+        }
+    }
+    // items across registers
+#pragma unroll
+    for (int rb = 0; rb < W::RB; ++rb) {
+        const XF<typename T_::MT> p = ph[W::LB + rb];
+#pragma unroll
+        for (int i = 0; i < W::RG; ++i) {
+            const bool set = (i >> rb) & 1;
+            if (BWD ? !set : set) A[i] = T_::add(A[i], T_::scale(A[i ^ (1 << rb)], p));
+        }
+    }
+}
+
+// Sum over the lanes of a team; the total lands in the team's last lane.
+template <int L, typename E>
+__device__ __forceinline__ E team_total(E x, int t)
+{
+    using W = WL<L, E>;
+    using T_ = ET<E>;
+#pragma unroll
+    for (int b = 0; b < W::LB; ++b) {
+        const E o = (b == 0)   ? lmove<0, false>(x)
+                    : (b == 1) ? lmove<1, false>(x)
+                    : (b == 2) ? lmove<2, false>(x)
+                    : (b == 3) ? lmove<3, false>(x)
+                    : (b == 4) ? lmove<4, false>(x)
+                               : lmove<5, false>(x);
+        const E nx = T_::add(x, o);
+        x = esel((t >> b) & 1, nx, x);
+    }
+    return x;
+}
+
+// Team context: its lanes, LDS staging of scaling factors, checkpoint scratch.
+template <int L, typename E>
+struct WTeam {
+    using M = typename ET<E>::MT;
+    int t;                 // lane inside the team
+    bool last;             // the team's last lane (holds team totals)
+    XF<M> *ph;             // LDS [CK][n] scaling factors of the staged block
+    E *ck;                 // scratch: checkpoints [blocks][D]
+};
+
+// Stage phi of the summed marginals at the positions of one block into LDS:
+// slot s is position x0 + s (s < cnt), item r is marginal r < j ? r : r + 1.
+template <int L, typename E>
+__device__ __forceinline__ void stage_phi(const WTeam<L, E> &tm, const double *__restrict__ a, long N, int j,
+                                          long x0, int cnt)
+{
+    using W = WL<L, E>;
+    using M = typename ET<E>::MT;
+    team_sync();
+    for (int k = tm.t; k < W::CK * W::n; k += W::TL) {
+        const int s = k / W::n, r = k - s * W::n;
+        const int q = r < j ? r : r + 1;
+        XF<M> v = xzero<M>();
+        if (s < cnt) v = xfrom_log<M>(a[(long)q * N + x0 + s]);
+        tm.ph[s * W::n + r] = v;
+    }
+    team_sync();
+}
+
+// Accumulator of a pass's per-position results (the FP64 estimate, residual or
+// objective terms), held by the team's last lane.
+struct WAcc {
+    double s;
+    XF<double> x;
+};
+
+// One product pass of marginal j over positions [p0, p1) of one instance on one
+// team, with the forward state at p0 - 1 (cf, or the empty placement if NULL)
+// and the complemented backward state at p1 (cb, or empty if NULL).  What is
+// done with log J_j(y) follows finish_lj (P_PRODUCT / P_UPDATE / P_CHECK); for
+// P_OBJECTIVE (E = DXF) the team's last lane accumulates phi_j(y) times the
+// cost-weighted product.  Returns the accumulated sum in the team's last lane.
+template <int L, typename E, int MODE>
+__device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int j, double *__restrict__ a,
+                          const double *__restrict__ log_u, double *__restrict__ out, long p0, long p1, const E *cf,
+                          const E *cb)
+{
+    using W = WL<L, E>;
+    using T_ = ET<E>;
+    constexpr int RG = W::RG, CK = W::CK, n = W::n, D = W::D;
+    const long N = I->N;
+    const int t = tm.t;
+    const int pt = popc(t);
+    const WConst<L, E> cF = wconst<L, E>(I->hoe, pt, 1);
+    const WConst<L, E> cB = wconst<L, E>(I->hoe, n - pt, -1);
+
+    WAcc acc = {0.0, xzero<double>()};
+    const long len = p1 - p0;
+    if (len <= 0) return acc;
+    const long nblk = (len + CK - 1) / CK;
+
+    // forward walk, checkpoint before every block
+    E A[RG];
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+        const int S = i * W::TL + t;
+        A[i] = cf ? cf[S] : esel(S == 0, T_::one(), T_::zero());
+    }
+    for (long b = 0; b < nblk; ++b) {
+        const long x0 = p0 + b * CK;
+        const int cnt = (int)min((long)CK, p1 - x0);
+#pragma unroll
+        for (int i = 0; i < RG; ++i) tm.ck[b * D + i * W::TL + t] = A[i];
+        if (b == nblk - 1) break;  // the last block's forward states are recomputed below
+        stage_phi<L, E>(tm, a, N, j, x0, cnt);
+        for (int s = 0; s < cnt; ++s) wstep<L, E, false>(A, tm.ph + s * n, cF, t);
+    }
+    team_sync();
+
+    // backward walk, block by block from the last
+    E Bs[RG];
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+        const int S = i * W::TL + t;
+        Bs[i] = cb ? cb[S] : esel(S == D - 1, T_::one(), T_::zero());
+    }
+    for (long b = nblk - 1; b >= 0; --b) {
+        const long x0 = p0 + b * CK;
+        const int cnt = (int)min((long)CK, p1 - x0);
+        stage_phi<L, E>(tm, a, N, j, x0, cnt);
+        // forward states of the block
+        E F[CK][RG];
+#pragma unroll
+        for (int i = 0; i < RG; ++i) A[i] = tm.ck[b * D + i * W::TL + t];
+#pragma unroll
+        for (int s = 0; s < CK; ++s) {
+            if (s < cnt) wstep<L, E, false>(A, tm.ph + s * n, cF, t);
+#pragma unroll
+            for (int i = 0; i < RG; ++i) F[s][i] = A[i];
+        }
+#pragma unroll
+        for (int s = CK - 1; s >= 0; --s) {
+            if (s >= cnt) continue;
+            const long y = x0 + s;
+            // J(y) = sum_S F_y(S) g(|R \ S|) B_{y+1}(R \ S)
+            E part = T_::zero();
+#pragma unroll
+            for (int i = 0; i < RG; ++i) {
+                const E hb = T_::disc(Bs[i], cB.g[popc(i)], cB.pc[popc(i)]);
+                part = (i == 0) ? T_::prod(F[s][i], hb) : T_::add(part, T_::prod(F[s][i], hb));
+            }
+            const E J = team_total<L, E>(part, t);
+            if (tm.last) {
+                if constexpr (MODE == P_OBJECTIVE) {
+                    const XF<double> ph = xfrom_log<double>(a[(long)j * N + y]);
+                    acc.x = xadd(acc.x, xmul(ph, J.w));
+                } else {
+                    acc.s += finish_lj<MODE>(xto_log(J), j, N, y, a, log_u, out);
+                }
+            }
+            wstep<L, E, true>(Bs, tm.ph + s * n, cB, t);
+        }
+    }
+    team_sync();
+    return acc;
+}
+
+}  // namespace mmot
+
+namespace mmot {
+
+// A value of the team's last lane, in every lane of the team.
+template <int L, typename E>
+__device__ __forceinline__ double team_bcast_last(double x)
+{
+    using W = WL<L, E>;
+    if constexpr (W::TPW == 1) {
+        return rlane(x, WAVE - 1);
+    } else {
+        const int src = (int)(threadIdx.x & (WAVE - 1)) | (W::TL - 1);
+        const long long b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffLL));
+        const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+}
+
+// Next instance ticket of a team, the same value in every lane of the team:
+// every lane takes part in the atomic (the team's first lane adds 1).
+template <int L, typename E>
+__device__ __forceinline__ int team_ticket(int *ticket, int t)
+{
+    using W = WL<L, E>;
+    const int v = atomicAdd(ticket, t == 0 ? 1 : 0);
+    if constexpr (W::TPW == 1) {
+        return __builtin_amdgcn_readfirstlane(v);
+    } else {
+        const int src = (int)(threadIdx.x & (WAVE - 1)) & ~(W::TL - 1);
+        return __builtin_amdgcn_ds_bpermute(src << 2, v);
+    }
+}
+
+// LDS bytes one team needs to stage scaling factors for every element kind.
+template <int L>
+struct WShared {
+    static constexpr int n = L - 1;
+    static constexpr int B32 = WL<L, XF<float>>::CK * n * (int)sizeof(XF<float>);
+    static constexpr int B64 = WL<L, XF<double>>::CK * n * (int)sizeof(XF<double>);
+    static constexpr int BOB = WL<L, DXF>::CK * n * (int)sizeof(XF<double>);
+    static constexpr int M1 = B32 > B64 ? B32 : B64;
+    static constexpr int BYTES = M1 > BOB ? M1 : BOB;
+    static constexpr int TPWMAX = WL<L, XF<float>>::TPW;  // TL does not depend on the element kind
+};
+
+static_assert(sizeof(XF<float>) == 8 && sizeof(XF<double>) == 16 && sizeof(DXF) == 32,
+              "element sizes assumed by wide_scratch_bytes");
+
+template <int L, typename E>
+__device__ __forceinline__ WTeam<L, E> make_team(char *lds, void *scratch)
+{
+    using W = WL<L, E>;
+    const int lane = threadIdx.x & (WAVE - 1);
+    WTeam<L, E> tm;
+    tm.t = lane & (W::TL - 1);
+    tm.last = tm.t == W::TL - 1;
+    tm.ph = reinterpret_cast<XF<typename ET<E>::MT> *>(lds + (lane / W::TL) * WShared<L>::BYTES);
+    tm.ck = reinterpret_cast<E *>(scratch);
+    return tm;
+}
+
+// Whole solve of one instance on one team (Alg. 1 loop: Gauss-Seidel updates in
+// precision M, FP64 residual, FP64 objective), same stopping rule as solve_one.
+template <int L, typename M>
+__device__ void wide_solve(char *lds, const Inst *__restrict__ I, const Ptrs P, const RunOpts o,
+                           Result *__restrict__ R)
+{
+    using EU = XF<M>;
+    const WTeam<L, EU> tu = make_team<L, EU>(lds, P.scratch);
+    const WTeam<L, XF<double>> tc = make_team<L, XF<double>>(lds, P.scratch);
+    const WTeam<L, DXF> to = make_team<L, DXF>(lds, P.scratch);
+    constexpr int TL = WL<L, EU>::TL;
+    const long N = I->N;
+    double *a = P.a;
+    const double *lu = P.log_u;
+    const int flags = o.flags | P.flags;
+    const long itr_max = P.itr_cap > 0 ? P.itr_cap : o.itr_max;
+
+    if (!(flags & F_WARM) && P.it0 == 0) {
+        // phi = 1/N (Alg. 1 initialisation)
+        const double a0 = -log((double)N);
+        for (long p = tu.t; p < (long)L * N; p += TL) a[p] = a0;
+        team_sync();
+    }
+    long it = P.it0;
+    int jr = P.j0;
+    double res = INFINITY, f = 1.0;
+    int status = ST_OK;
+    bool checked = false;
+    while (it < itr_max || jr > 0) {
+        const bool resumed = jr > 0;
+        if (!resumed) ++it;
+        double est = 0.0;
+        for (int j = jr; j < L; ++j) {
+            const WAcc e = wide_pass<L, EU, P_UPDATE>(tu, I, j, a, lu, nullptr, 0, N, nullptr, nullptr);
+            if (j < L - 1) est += e.s;
+        }
+        est = team_bcast_last<L, EU>(est);
+        jr = 0;
+        const bool trig = !resumed && o.tol >= 0.0 && est <= o.tol * f;
+        const bool chk = !(flags & F_NO_CHECK) &&
+                         ((resumed && P.j0 == L) || (o.check_every > 0 && it % o.check_every == 0) ||
+                          it >= itr_max || trig);
+        if (chk) {
+            checked = true;
+            double r = 0.0;
+            for (int j = 0; j < L - 1; ++j)
+                r += wide_pass<L, XF<double>, P_CHECK>(tc, I, j, a, lu, nullptr, 0, N, nullptr, nullptr).s;
+            res = team_bcast_last<L, EU>(r);
+            if (!(res == res)) {
+                status = ST_NUMERIC;
+                break;
+            }
+            if (res <= o.tol) break;
+            if (trig) f *= 0.5;
+        }
+    }
+    double W = 0.0;
+    if (status == ST_OK && !(flags & F_NO_OBJ)) {
+        const WAcc w = wide_pass<L, DXF, P_OBJECTIVE>(to, I, L - 1, a, lu, nullptr, 0, N, nullptr, nullptr);
+        W = I->h * xto_double(w.x);
+        if (!(W == W) || W == INFINITY) status = ST_NUMERIC;
+    }
+    if (status == ST_OK && checked && o.tol >= 0.0 && !(res <= o.tol)) status = ST_NOT_CONVERGED;
+    if (tu.last) {
+        R->W = W;
+        R->marg_err = res;
+        R->iters = it;
+        R->status = status;
+        R->l = L;
+        R->N = N;
+    }
+}
+
+// Persistent batch of l = L instances: each team takes the next instance ticket
+// until the list is exhausted.
+template <int L, typename M>
+__global__ __launch_bounds__(64) void k_wide_batch(const Inst *I, const Ptrs *P, const int *order, int count,
+                                                   RunOpts o, Result *R, int *ticket)
+{
+    __shared__ __attribute__((aligned(16))) char lds[WShared<L>::TPWMAX * WShared<L>::BYTES];
+    const int t = (int)threadIdx.x & (WL<L, XF<M>>::TL - 1);
+    for (;;) {
+        const int tk = team_ticket<L, XF<M>>(ticket, t);
+        if (tk >= count) break;
+        const int idx = order[tk];
+        wide_solve<L, M>(lds, &I[idx], P[idx], o, &R[idx]);
+    }
+}
+
+// One product (MODE P_PRODUCT, element XF<M>) or the objective (P_OBJECTIVE, DXF)
+// of one instance on the first team of one wavefront.
+template <int L, typename E, int MODE>
+__global__ __launch_bounds__(64) void k_wide_pass(const Inst *I, Ptrs P, int j, double *result)
+{
+    __shared__ __attribute__((aligned(16))) char lds[WShared<L>::TPWMAX * WShared<L>::BYTES];
+    if (threadIdx.x >= WL<L, E>::TL) return;
+    const WTeam<L, E> tm = make_team<L, E>(lds, P.scratch);
+    const WAcc r = wide_pass<L, E, MODE>(tm, I, j, P.a, P.log_u, P.out, 0, I->N, nullptr, nullptr);
+    if (tm.last && result) result[0] = (MODE == P_OBJECTIVE) ? I->h * xto_double(r.x) : r.s;
+}
+
+// FP64 errors of all l marginals of one instance.
+template <int L>
+__global__ __launch_bounds__(64) void k_wide_check_all(const Inst *I, Ptrs P, double *err)
+{
+    __shared__ __attribute__((aligned(16))) char lds[WShared<L>::TPWMAX * WShared<L>::BYTES];
+    if (threadIdx.x >= WL<L, XF<double>>::TL) return;
+    const WTeam<L, XF<double>> tm = make_team<L, XF<double>>(lds, P.scratch);
+    for (int j = 0; j < L; ++j) {
+        const WAcc r = wide_pass<L, XF<double>, P_CHECK>(tm, I, j, P.a, P.log_u, nullptr, 0, I->N, nullptr, nullptr);
+        if (tm.last) err[j] = r.s;
+    }
+}
+
+}  // namespace mmot

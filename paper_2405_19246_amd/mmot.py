@@ -20,7 +20,7 @@ OK, ERR_INVALID, ERR_NOMEM, ERR_NUMERIC, NOT_CONVERGED, ERR_UNSUPPORTED, ERR_HIP
 FP64, FP32 = 0, 1
 FLAG_WARM_START = 1
 FLAG_NO_FAST = 2
-MAX_L = 8
+MAX_L = 10
 
 _c_d, _c_i32, _c_i64, _c_p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
 
