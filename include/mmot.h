@@ -82,6 +82,7 @@ typedef struct {
 
 #define MMOT_FLAG_WARM_START 1
 #define MMOT_FLAG_NO_FAST 2
+#define MMOT_FLAG_TILES 4
 
 /* Per-solve outcome. */
 typedef struct {

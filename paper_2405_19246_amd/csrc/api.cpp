@@ -70,7 +70,15 @@ struct mmot_plan {
     size_t scratch_size = 0;
     Result *dR = nullptr;
     double *dtmp = nullptr;
+    // tiled plans (long N): tile shape, host copies kept alive for async uploads
+    bool tiled = false;
+    int ntile = 1, B = 0;
+    TileInst hTI;
+    mutable Ptrs hP;
+    mutable std::vector<char> jobs_host;
 };
+
+static int plan_flags(const mmot_opts &o) { return (o.flags & MMOT_FLAG_TILES) ? F_TILES : 0; }
 
 extern "C" {
 
@@ -96,13 +104,19 @@ int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_
     pl->s = (hipStream_t)hip_stream;
     const Inst I = make_inst(p->l, p->N, p->h, p->eps);
     pl->hI = I;
-    pl->scratch_size = scratch_bytes(p->l, p->N, p->precision);
+    pl->tiled = tile_shape(p->l, p->N, plan_flags(oo), &pl->ntile, &pl->B);
+    pl->scratch_size = scratch_bytes(p->l, p->N, p->precision, plan_flags(oo));
     hipError_t e = hipMalloc((void **)&pl->dI, sizeof(Inst));
     if (e == hipSuccess) e = hipMalloc(&pl->scratch, std::max<size_t>(pl->scratch_size, 256));
     if (e == hipSuccess) e = hipMalloc((void **)&pl->dR, sizeof(Result));
     if (e == hipSuccess) e = hipMalloc((void **)&pl->dtmp, sizeof(double) * MAXL);
     if (e == hipSuccess) e = batch_buffers_alloc(&pl->bb, 1);
     if (e == hipSuccess) e = hipMemcpy(pl->dI, &I, sizeof(Inst), hipMemcpyHostToDevice);
+    if (e == hipSuccess && pl->tiled) {
+        pl->hTI = tile_inst(p->l, pl->ntile, pl->B, reinterpret_cast<char *>(pl->scratch));
+        e = hipMemcpy(pl->bb.dTI, &pl->hTI, sizeof(TileInst), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(pl->bb.dI, &I, sizeof(Inst), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         mmot_plan_destroy(pl);
         return fail(e == hipErrorOutOfMemory ? MMOT_ERR_NOMEM : MMOT_ERR_HIP,
@@ -133,10 +147,47 @@ int mmot_plan_destroy(mmot_plan_t *pl)
     return MMOT_OK;
 }
 
+// One tiled pass (product, FP64 errors of every marginal, or objective) of a
+// tiled plan; per-tile sums land in the plan's scratch (TileInst.part).
+static int plan_tile_pass(const mmot_plan_t *pl, int mode, int j, const double *log_u, const double *log_phi,
+                          double *out)
+{
+    pl->hP = {log_u, const_cast<double *>(log_phi), out, pl->scratch, 0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(pl->bb.dP, &pl->hP, sizeof(Ptrs), hipMemcpyHostToDevice, pl->s));
+    TileJobs J;
+    std::vector<TileInst> hti(1, pl->hTI);
+    HIPCHK(upload_jobs(std::vector<int>{0}, hti, pl->p.l, &pl->bb, pl->s, pl->jobs_host, &J));
+    if (mode == P_CHECK) {
+        for (int jj = 0; jj < pl->p.l; ++jj)
+            HIPCHK(launch_tile_pass(pl->p.l, MMOT_FP64, P_CHECK, pl->bb.dI, pl->bb.dP, pl->bb.dTI, nullptr, J, jj, 0,
+                                    pl->s));
+    } else {
+        HIPCHK(launch_tile_pass(pl->p.l, pl->p.precision, mode, pl->bb.dI, pl->bb.dP, pl->bb.dTI, nullptr, J, j, 0,
+                                pl->s));
+    }
+    return MMOT_OK;
+}
+
+// Sums of the per-tile results of rows [j0, j1) of a tiled plan (synchronises).
+static int plan_tile_sums(const mmot_plan_t *pl, int j0, int j1, double *sums)
+{
+    std::vector<double> part((size_t)(j1 - j0) * pl->ntile);
+    HIPCHK(hipMemcpyAsync(part.data(), pl->hTI.part + (size_t)j0 * pl->ntile, sizeof(double) * part.size(),
+                          hipMemcpyDeviceToHost, pl->s));
+    HIPCHK(hipStreamSynchronize(pl->s));
+    for (int j = j0; j < j1; ++j) {
+        double r = 0.0;
+        for (int t = 0; t < pl->ntile; ++t) r += part[(size_t)(j - j0) * pl->ntile + t];
+        sums[j - j0] = r;
+    }
+    return MMOT_OK;
+}
+
 int mmot_marginal_product(const mmot_plan_t *pl, int32_t j, const double *log_phi, double *log_J)
 {
     if (!pl || !log_phi || !log_J) return fail(MMOT_ERR_INVALID, "NULL argument");
     if (j < 0 || j >= pl->p.l) return fail(MMOT_ERR_INVALID, "j out of range");
+    if (pl->tiled) return plan_tile_pass(pl, P_PRODUCT, j, nullptr, log_phi, log_J);
     Ptrs P = {nullptr, const_cast<double *>(log_phi), log_J, pl->scratch, 0, 0, 0, 0};
     HIPCHK(launch_pass(pl->p.l, pl->p.precision, 0, pl->dI, P, j, nullptr, pl->s));
     return MMOT_OK;
@@ -145,6 +196,10 @@ int mmot_marginal_product(const mmot_plan_t *pl, int32_t j, const double *log_ph
 int mmot_marginal_errors(const mmot_plan_t *pl, const double *log_u, const double *log_phi, double *err)
 {
     if (!pl || !log_u || !log_phi || !err) return fail(MMOT_ERR_INVALID, "NULL argument");
+    if (pl->tiled) {
+        const int rc = plan_tile_pass(pl, P_CHECK, 0, log_u, log_phi, nullptr);
+        return rc ? rc : plan_tile_sums(pl, 0, pl->p.l, err);
+    }
     Ptrs P = {log_u, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
     HIPCHK(launch_pass(pl->p.l, MMOT_FP64, 2, pl->dI, P, 0, pl->dtmp, pl->s));
     HIPCHK(hipMemcpyAsync(err, pl->dtmp, sizeof(double) * pl->p.l, hipMemcpyDeviceToHost, pl->s));
@@ -152,7 +207,10 @@ int mmot_marginal_errors(const mmot_plan_t *pl, const double *log_u, const doubl
     return MMOT_OK;
 }
 
-static int plan_path(const mmot_plan_t *pl) { return (pl->o.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0; }
+static int plan_path(const mmot_plan_t *pl)
+{
+    return ((pl->o.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | plan_flags(pl->o);
+}
 
 int mmot_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_phi, int64_t n_sweeps,
                        double *marg_err)
@@ -202,6 +260,12 @@ int mmot_solve(const mmot_plan_t *pl, const double *log_u, double *log_phi, mmot
 int mmot_objective(const mmot_plan_t *pl, const double *log_phi, double *W)
 {
     if (!pl || !log_phi || !W) return fail(MMOT_ERR_INVALID, "NULL argument");
+    if (pl->tiled) {
+        int rc = plan_tile_pass(pl, P_OBJECTIVE, pl->p.l - 1, nullptr, log_phi, nullptr);
+        if (!rc) rc = plan_tile_sums(pl, pl->p.l - 1, pl->p.l, W);
+        if (rc) return rc;
+        return std::isfinite(*W) ? MMOT_OK : fail(MMOT_ERR_NUMERIC, "non-finite objective");
+    }
     Ptrs P = {nullptr, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
     HIPCHK(launch_pass(pl->p.l, MMOT_FP64, 3, pl->dI, P, pl->p.l - 1, pl->dtmp, pl->s));
     HIPCHK(hipMemcpyAsync(W, pl->dtmp, sizeof(double), hipMemcpyDeviceToHost, pl->s));
@@ -306,6 +370,8 @@ hipError_t batch_buffers_alloc(BatchBuffers *bb, size_t c)
     if (e == hipSuccess) e = hipMalloc((void **)&bb->dR, sizeof(Result) * c);
     if (e == hipSuccess) e = hipMalloc((void **)&bb->dticket, sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&bb->dT, sizeof(Track) * c);
+    if (e == hipSuccess) e = hipMalloc((void **)&bb->dTI, sizeof(TileInst) * c);
+    if (e == hipSuccess) e = hipMalloc((void **)&bb->dTT, sizeof(TileTrack) * c);
     return e;
 }
 
@@ -317,6 +383,9 @@ void batch_buffers_free(BatchBuffers *bb)
     if (bb->dR) (void)hipFree(bb->dR);
     if (bb->dticket) (void)hipFree(bb->dticket);
     if (bb->dT) (void)hipFree(bb->dT);
+    if (bb->dTI) (void)hipFree(bb->dTI);
+    if (bb->dTT) (void)hipFree(bb->dTT);
+    if (bb->djobs) (void)hipFree(bb->djobs);
     *bb = {};
 }
 
@@ -353,24 +422,36 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     auto by_cost = [&](std::vector<int> &v) {
         std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     };
-    std::vector<int> robust, group[MAXL + 1], wide[MAXL + 1];
+    // Paths: tiled (long N), one team per instance (l >= WIDE_MINL), register-resident
+    // (l <= 4, N fits a workgroup), one wavefront per instance (the rest).  Index p
+    // of robust / wide / tiled is the precision of the instance's scans: FP32 mode
+    // keeps FP32 mantissas only where the scan window is short (scan_precision).
+    std::vector<int> robust[2], group[MAXL + 1], wide[MAXL + 1][2], tiled[MAXL + 1][2];
     for (int i = 0; i < count; ++i) {
-        if (hI[i].l >= WIDE_MINL) wide[hI[i].l].push_back(i);
+        int nt = 0, tb = 0;
+        const int p = scan_precision(hI[i], precision);
+        if (tile_shape(hI[i].l, hI[i].N, flags | hP[i].flags, &nt, &tb)) tiled[hI[i].l][p].push_back(i);
+        else if (hI[i].l >= WIDE_MINL) wide[hI[i].l][p].push_back(i);
         else if (!(flags & F_NO_FAST) && fast_eligible(hI[i], precision)) group[hI[i].l].push_back(i);
-        else robust.push_back(i);
+        else robust[p].push_back(i);
     }
-    by_cost(robust);
-    // dorder: [robust | wide 7 | wide 8 | ... | group 2 | group 3 | ...], then the second half for
-    // resumed and objective lists
+    // dorder: [robust FP64 | robust FP32 | wide (l, p) ... | group 2 | group 3 | ...], then the second
+    // half for resumed and objective lists
     std::vector<int> order;
     order.reserve(2 * (size_t)count);
-    order.insert(order.end(), robust.begin(), robust.end());
-    int woff[MAXL + 1] = {0};
-    for (int l = WIDE_MINL; l <= MAXL; ++l) {
-        by_cost(wide[l]);
-        woff[l] = (int)order.size();
-        order.insert(order.end(), wide[l].begin(), wide[l].end());
+    int roff[2] = {0, 0};
+    for (int p = 0; p < 2; ++p) {
+        by_cost(robust[p]);
+        roff[p] = (int)order.size();
+        order.insert(order.end(), robust[p].begin(), robust[p].end());
     }
+    int woff[MAXL + 1][2] = {};
+    for (int l = WIDE_MINL; l <= MAXL; ++l)
+        for (int p = 0; p < 2; ++p) {
+            by_cost(wide[l][p]);
+            woff[l][p] = (int)order.size();
+            order.insert(order.end(), wide[l][p].begin(), wide[l][p].end());
+        }
     int goff[MAXL + 1] = {0}, gmaxN[MAXL + 1] = {0};
     for (int l = 2; l <= MAXL; ++l) {
         by_cost(group[l]);
@@ -381,9 +462,9 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     HIPCHK(hipMemcpyAsync(bb->dI, hI, sizeof(Inst) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(bb->dP, hP, sizeof(Ptrs) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(bb->dorder, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
-    size_t nwide = 0;
-    for (int l = WIDE_MINL; l <= MAXL; ++l) nwide += wide[l].size();
-    const bool any_fast = robust.size() + nwide < (size_t)count;
+    size_t nother = robust[0].size() + robust[1].size();
+    for (int l = 2; l <= MAXL; ++l) nother += wide[l][0].size() + wide[l][1].size() + tiled[l][0].size() + tiled[l][1].size();
+    const bool any_fast = nother < (size_t)count;
     std::vector<Track> hT;
     if (any_fast) {
         hT.resize(count);
@@ -411,20 +492,33 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     const bool tmon = timed;
     auto tbegin = [&](int kind) { return tmon ? tm.begin(kind, s, &slot) : hipSuccess; };
     auto tend = [&]() { return tmon ? tm.end(slot, s) : hipSuccess; };
-    if (!robust.empty()) {
-        const int n = (int)robust.size();
+    for (int p = 0; p < 2; ++p) {
+        if (robust[p].empty()) continue;
+        const int n = (int)robust[p].size();
         const int blocks = std::max(1, std::min((n + 3) / 4, 4096));
         HIPCHK(tbegin(2));
-        HIPCHK(launch_solve_batch(precision, bb->dI, bb->dP, bb->dorder, n, o, bb->dR, bb->dticket, blocks, s));
+        HIPCHK(launch_solve_batch(p, bb->dI, bb->dP, bb->dorder + roff[p], n, o, bb->dR, bb->dticket, blocks, s));
         HIPCHK(tend());
     }
-    for (int l = WIDE_MINL; l <= MAXL; ++l) {
-        if (wide[l].empty()) continue;
-        HIPCHK(tbegin(2));
-        HIPCHK(launch_wide_batch(l, precision, bb->dI, bb->dP, bb->dorder + woff[l], (int)wide[l].size(), o, bb->dR,
-                                 bb->dticket, s));
-        HIPCHK(tend());
-    }
+    for (int l = WIDE_MINL; l <= MAXL; ++l)
+        for (int p = 0; p < 2; ++p) {
+            if (wide[l][p].empty()) continue;
+            HIPCHK(tbegin(2));
+            HIPCHK(launch_wide_batch(l, p, bb->dI, bb->dP, bb->dorder + woff[l][p], (int)wide[l][p].size(), o,
+                                     bb->dR, bb->dticket, s));
+            HIPCHK(tend());
+        }
+    // tiled instances: host-driven blocks of sweeps per (l, precision), results straight into hR
+    std::vector<Result> tiled_res;
+    for (int l = 2; l <= MAXL; ++l)
+        for (int p = 0; p < 2; ++p) {
+            if (tiled[l][p].empty()) continue;
+            if (tiled_res.empty()) tiled_res.resize(count);
+            HIPCHK(tbegin(2));
+            const int rc = tiled_group_solve(l, tiled[l][p], count, hI, hP, p, o, flags, s, bb, tiled_res.data());
+            if (rc) return rc;
+            HIPCHK(tend());
+        }
     std::vector<int> resumed, objective;
     std::vector<char> handed(count, 0);  // handed to the extended-range solver
     if (any_fast) {
@@ -524,6 +618,9 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     if (timed) HIPCHK(hipEventRecord(g_ev1, s));
     HIPCHK(hipMemcpyAsync(hR, bb->dR, sizeof(Result) * count, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    for (int l = 2; l <= MAXL; ++l)
+        for (int p = 0; p < 2; ++p)
+            for (int i : tiled[l][p]) hR[i] = tiled_res[i];
     if (timed) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, g_ev0, g_ev1));
@@ -607,7 +704,7 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
         if (!inst[i].log_u || !inst[i].log_phi) return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": NULL buffer");
         hI[i] = make_inst(inst[i].l, inst[i].N, inst[i].h, inst[i].eps);
         offs[i] = off;
-        off += scratch_bytes(inst[i].l, inst[i].N, precision);
+        off += scratch_bytes(inst[i].l, inst[i].N, precision, (o->flags & MMOT_FLAG_TILES) ? F_TILES : 0);
     }
     std::lock_guard<std::mutex> lk(g_batch.mu);
     rc = g_batch.reserve((size_t)count, std::max<size_t>(off, 256));
@@ -615,7 +712,8 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
     for (int i = 0; i < count; ++i)
         hP[i] = {inst[i].log_u, inst[i].log_phi, nullptr, g_batch.scratch + offs[i], 0, 0,
                  (o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0, 0};
-    RunOpts ro = {o->tol, o->itr_max, o->check_every, (o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0, 0,
+    RunOpts ro = {o->tol, o->itr_max, o->check_every,
+                  ((o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | ((o->flags & MMOT_FLAG_TILES) ? F_TILES : 0), 0,
                   FAST_WARMUP_SWEEPS};
     BatchBuffers bb = g_batch.bb;
     std::vector<Result> hR(count);

@@ -41,22 +41,37 @@ def _units():
         units.append((os.path.join(HERE, "k_single.hip"), "k_single_l%d.o" % l, ["-DMMOT_L=%d" % l]))
     for l in range(7, WMAX + 1):
         units.append((os.path.join(HERE, "k_wide.hip"), "k_wide_l%d.o" % l, ["-DMMOT_L=%d" % l]))
+    for l in range(2, WMAX + 1):
+        units.append((os.path.join(HERE, "k_tile.hip"), "k_tile_l%d.o" % l, ["-DMMOT_L=%d" % l]))
     units.append((os.path.join(HERE, "k_batch.hip"), "k_batch.o", []))
     units.append((os.path.join(HERE, "api.cpp"), "api.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "serve.cpp"), "serve.o", ["-x", "hip"]))
+    units.append((os.path.join(HERE, "tile.cpp"), "tile.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "tables.cpp"), "tables.o", []))
     return units
 
 
-def _stale(obj: str) -> bool:
-    """True if obj is missing or older than any source or header of the library."""
+def _includes(path: str, seen: set) -> set:
+    """Files of this directory (and include/) that path includes, transitively."""
+    import re
+    for name in re.findall(r'#include\s+"([^"]+)"', open(path).read()):
+        for d in (HERE, os.path.join(ROOT, "include")):
+            f = os.path.join(d, name)
+            if os.path.exists(f) and f not in seen:
+                seen.add(f)
+                _includes(f, seen)
+    return seen
+
+
+def _stale(unit) -> bool:
+    """True if the unit's object is missing or older than its source or a header it includes."""
+    src, obj, _ = unit
     path = os.path.join(BUILD, obj)
     if not os.path.exists(path):
         return True
     t = os.path.getmtime(path)
-    srcs = [os.path.join(HERE, f) for f in os.listdir(HERE) if f.endswith((".hpp", ".hip", ".cpp"))]
-    srcs.append(os.path.join(ROOT, "include", "mmot.h"))
-    return any(os.path.getmtime(f) > t for f in srcs)
+    deps = _includes(src, {src})
+    return any(os.path.getmtime(f) > t for f in deps)
 
 
 def _compile(args):
@@ -74,8 +89,8 @@ def build(jobs: int | None = None, verbose: bool = True, only_stale: bool = Fals
     os.makedirs(BUILD, exist_ok=True)
     units = _units()
     if only_stale:
-        keep = [u for u in units if not _stale(u[1])]
-        units = [u for u in units if _stale(u[1])]
+        keep = [u for u in units if not _stale(u)]
+        units = [u for u in units if _stale(u)]
     else:
         keep = []
     jobs = jobs or max(1, min(len(units), os.cpu_count() or 4))

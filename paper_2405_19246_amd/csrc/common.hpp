@@ -100,6 +100,9 @@ struct RunOpts {
     int32_t warmup;       // batch host: sweeps of the first round, after which the batch is reordered (0: none)
 };
 
+// What a marginal pass does with log J_j (scan.hpp finish_lj, wide.hpp).
+enum PassMode { P_PRODUCT = 0, P_UPDATE = 1, P_CHECK = 2, P_OBJECTIVE = 3 };
+
 // Same layout as mmot_result.
 struct Result {
     double W;
@@ -115,6 +118,7 @@ constexpr int32_t F_WARM = 1;        // keep the given potentials
 constexpr int32_t F_NO_CHECK = 2;    // no residual check at all
 constexpr int32_t F_NO_OBJ = 4;      // skip the objective
 constexpr int32_t F_NO_FAST = 8;     // host only: every instance on the extended-range solver
+constexpr int32_t F_TILES = 16;      // host only: every instance is tiled (tests and small shapes)
 
 // Lane width V per (l, pass kind) -- trades registers against scan overhead.
 // kind 0: FP32 update, 1: FP64 update and product, 2: FP64 objective
@@ -189,5 +193,30 @@ constexpr long wide_scratch_bytes(int l, long N)
                : (wide_ck_bytes(l, 3, 16, N) > wide_ck_bytes(l, 6, 32, N) ? wide_ck_bytes(l, 3, 16, N)
                                                                           : wide_ck_bytes(l, 6, 32, N));
 }
+
+// Per-instance buffers and shape of a tiled solve.
+struct TileInst {
+    int32_t ntile;   // tiles
+    int32_t B;       // positions per tile (the last may be shorter)
+    char *agg;       // [ntile][2][l][2^(l-1)] elements: Q_m, m = 0..l-1 (index space of the team)
+    char *carry;     // [ntile][2][2^(l-1)] elements: state entering each tile (index space)
+    char *ck;        // [ntile][ck_stride] checkpoint scratch of the final passes
+    double *part;    // [l][ntile] per-tile sums of the update / check passes
+    long ck_stride;  // bytes of checkpoint scratch per tile
+};
+
+// State of one instance across the launches of a tiled solve.
+struct TileTrack {
+    double f;        // the estimate asks for a check once it falls below tol * f
+    double est;      // marginal-error estimate of the last sweep
+    double res;      // last FP64 residual (+inf before the first)
+    int64_t it;      // sweeps done
+    int32_t state;   // TS_SWEEP, TS_CHECK or TS_DONE
+    int32_t status;  // final status once TS_DONE
+    int32_t checked; // a residual has been taken
+    int32_t pad;
+};
+
+constexpr int32_t TS_OBJ = 4;  // tiled solves: objective pending
 
 }  // namespace mmot

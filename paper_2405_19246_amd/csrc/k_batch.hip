@@ -2,10 +2,22 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "wide.hpp"
 
 namespace mmot {
 
 __global__ void k_fill_int(int *p, int v) { *p = v; }
+
+// phi = 1/N (Alg. 1 initialisation) for the listed instances that do not start warm.
+__global__ void k_tile_init(const Inst *I, const Ptrs *P, const int *list, int count, RunOpts o)
+{
+    if ((int)blockIdx.y >= count) return;
+    const int i = list[blockIdx.y];
+    if ((o.flags | P[i].flags) & F_WARM) return;
+    const long n = (long)I[i].l * I[i].N;
+    const double a0 = -log((double)I[i].N);
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) P[i].a[p] = a0;
+}
 
 __global__ __launch_bounds__(256) void k_objective_batch(const Inst *I, const Ptrs *P, const int *list, int count,
                                                          Result *R, int *ticket)
@@ -77,6 +89,40 @@ hipError_t launch_pass(int l, int precision, int mode, const Inst *dI, const Ptr
         default: break;
     }
     MMOT_DISPATCH(launch_pass_l, l, precision, mode, dI, P, j, dres, s)
+}
+
+#define MMOT_DISPATCH_T(fn, l, ...)              \
+    switch (l) {                                  \
+        case 2: return fn##2(__VA_ARGS__);        \
+        case 3: return fn##3(__VA_ARGS__);        \
+        case 4: return fn##4(__VA_ARGS__);        \
+        case 5: return fn##5(__VA_ARGS__);        \
+        case 6: return fn##6(__VA_ARGS__);        \
+        case 7: return fn##7(__VA_ARGS__);        \
+        case 8: return fn##8(__VA_ARGS__);        \
+        case 9: return fn##9(__VA_ARGS__);        \
+        case 10: return fn##10(__VA_ARGS__);      \
+        default: return hipErrorInvalidValue;     \
+    }
+
+hipError_t launch_tile_pass(int l, int precision, int mode, const Inst *dI, const Ptrs *dP, const TileInst *dTI,
+                            const TileTrack *dTr, const TileJobs &J, int j, int state_need, hipStream_t s)
+{
+    MMOT_DISPATCH_T(launch_tile_pass_l, l, precision, mode, dI, dP, dTI, dTr, J, j, state_need, s)
+}
+
+hipError_t launch_tile_ctrl(int l, int which, const Ptrs *dP, const TileInst *dTI, TileTrack *dTr, int count,
+                            const RunOpts &o, hipStream_t s)
+{
+    MMOT_DISPATCH_T(launch_tile_ctrl_l, l, which, dP, dTI, dTr, count, o, s)
+}
+
+hipError_t launch_tile_init(const Inst *dI, const Ptrs *dP, const int *dlist, int count, const RunOpts &o,
+                            hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_init, dim3(64, count), dim3(256), 0, s, dI, dP, dlist, count, o);
+    return hipGetLastError();
 }
 
 hipError_t launch_wide_batch(int l, int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,

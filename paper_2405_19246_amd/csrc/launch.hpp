@@ -32,6 +32,47 @@ MMOT_DECL_L(5)
 MMOT_DECL_L(6)
 #undef MMOT_DECL_L
 
+// Job lists of the tiled launches (device arrays): agg (instance, tile, m,
+// direction), chain (instance, direction), fin (instance, tile).
+struct TileJobs {
+    const int4 *agg;
+    int n1;
+    const int2 *chain;
+    int n2;
+    const int2 *fin;
+    int n3;
+};
+
+#define MMOT_DECL_T(l)                                                                                          \
+    hipError_t launch_tile_pass_l##l(int precision, int mode, const Inst *dI, const Ptrs *dP, const TileInst *dTI, \
+                                     const TileTrack *dTr, const TileJobs &J, int j, int state_need,            \
+                                     hipStream_t s);                                                            \
+    hipError_t launch_tile_ctrl_l##l(int which, const Ptrs *dP, const TileInst *dTI, TileTrack *dTr, int count,   \
+                                     const RunOpts &o, hipStream_t s);
+MMOT_DECL_T(2)
+MMOT_DECL_T(3)
+MMOT_DECL_T(4)
+MMOT_DECL_T(5)
+MMOT_DECL_T(6)
+MMOT_DECL_T(7)
+MMOT_DECL_T(8)
+MMOT_DECL_T(9)
+MMOT_DECL_T(10)
+#undef MMOT_DECL_T
+
+// Tiled passes of marginal j (mode P_PRODUCT / P_UPDATE in the given precision,
+// P_CHECK and P_OBJECTIVE in FP64) over the jobs of instances with this l; jobs
+// of instances whose TileTrack.state differs from state_need do nothing
+// (dTr NULL: every job runs).
+hipError_t launch_tile_pass(int l, int precision, int mode, const Inst *dI, const Ptrs *dP, const TileInst *dTI,
+                            const TileTrack *dTr, const TileJobs &J, int j, int state_need, hipStream_t s);
+// which 0: estimate and check decision after a sweep; 1: residual and stop decision after a check.
+hipError_t launch_tile_ctrl(int l, int which, const Ptrs *dP, const TileInst *dTI, TileTrack *dTr, int count,
+                            const RunOpts &o, hipStream_t s);
+// phi = 1/N for the listed instances that do not start warm.
+hipError_t launch_tile_init(const Inst *dI, const Ptrs *dP, const int *dlist, int count, const RunOpts &o,
+                            hipStream_t s);
+
 // Team-layout kernels (wide.hpp), l = WIDE_MINL .. WIDE_MAXL.
 #define MMOT_DECL_W(l)                                                                                      \
     hipError_t launch_wide_pass_l##l(int precision, int mode, const Inst *dI, const Ptrs &P, int j, double *dres, \

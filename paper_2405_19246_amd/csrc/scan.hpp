@@ -335,7 +335,6 @@ __device__ __forceinline__ const Disc<M> *upd_disc(const Inst *I)
         return &I->d64;
 }
 
-enum PassMode { P_PRODUCT = 0, P_UPDATE = 1, P_CHECK = 2, P_OBJECTIVE = 3 };
 
 template <typename E>
 __device__ __forceinline__ void store_elem(void *base, long idx, int lane_ok, E x)

@@ -110,10 +110,10 @@ struct Done {
     std::vector<double> log_phi;
 };
 
-size_t request_bytes(int l, int64_t N, int precision)
+size_t request_bytes(int l, int64_t N, int precision, int flags)
 {
     const size_t rows = Arena::round_up(sizeof(double) * (size_t)l * (size_t)N);
-    return 2 * rows + scratch_bytes(l, N, precision);
+    return 2 * rows + scratch_bytes(l, N, precision, flags);
 }
 
 }  // namespace
@@ -136,7 +136,8 @@ struct mmot_server {
 
     void loop();
     int finish(std::vector<Slot> &slots, const std::vector<int> &fin, const std::vector<Result> &hR);
-    int path_flag() const { return (cfg.opts.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0; }
+    int tile_flag() const { return (cfg.opts.flags & MMOT_FLAG_TILES) ? F_TILES : 0; }
+    int path_flag() const { return ((cfg.opts.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | tile_flag(); }
 };
 
 int mmot_server::finish(std::vector<Slot> &slots, const std::vector<int> &fin, const std::vector<Result> &hR)
@@ -202,7 +203,7 @@ void mmot_server::loop()
             // admit in arrival order while a slot and arena space are free
             while (!queue.empty() && (int)slots.size() < cfg.max_slots) {
                 Request &r = *queue.front();
-                const size_t need = request_bytes(r.l, r.N, cfg.precision);
+                const size_t need = request_bytes(r.l, r.N, cfg.precision, tile_flag());
                 size_t off = 0;
                 if (!arena.alloc(need, &off)) break;
                 Slot sl;
@@ -336,7 +337,7 @@ int mmot_serve_submit(mmot_server_t *srv, const mmot_request *req, uint64_t *tic
         }
         if (!(std::fabs(mass - 1.0) <= 1e-9)) return fail(MMOT_ERR_INVALID, "each marginal must sum to 1");
     }
-    if (request_bytes(req->l, req->N, srv->cfg.precision) > srv->cfg.hbm_budget_bytes)
+    if (request_bytes(req->l, req->N, srv->cfg.precision, srv->tile_flag()) > srv->cfg.hbm_budget_bytes)
         return fail(MMOT_ERR_NOMEM, "request footprint exceeds the server's HBM budget");
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stopping) return fail(MMOT_ERR_STATE, "server is stopping");

@@ -3,8 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "common.hpp"
+#include "launch.hpp"
 #include "mmot.h"
 #include "tables.hpp"
 
@@ -19,7 +21,25 @@ struct BatchBuffers {
     Result *dR;
     int *dticket;
     Track *dT;
+    TileInst *dTI;    // tiled solves: per-instance buffers
+    TileTrack *dTT;   // tiled solves: per-instance state
+    char *djobs;      // tiled solves: job lists (grow-only)
+    size_t jobs_cap;
 };
+
+// Job lists of the tiled launches of instances g (all with l marginals) in bb's
+// job buffer; host keeps the uploaded bytes until the stream has copied them.
+hipError_t upload_jobs(const std::vector<int> &g, const std::vector<TileInst> &hTI, int l, BatchBuffers *bb,
+                       hipStream_t s, std::vector<char> &host, TileJobs *J);
+
+// Grows bb's job-list buffer to at least jobs_bytes.
+hipError_t tile_buffers_reserve(BatchBuffers *bb, size_t jobs_bytes);
+
+// Tiled solves of the instances g (all with l marginals) of a batch of count:
+// sweeps in blocks of launches until each stops, then the FP64 objective; fills
+// hR[i] for i in g.  dI/dP of bb hold the batch's descriptors already.
+int tiled_group_solve(int l, const std::vector<int> &g, int count, const Inst *hI, const Ptrs *hP, int precision,
+                      const RunOpts &o, int flags, hipStream_t s, BatchBuffers *bb, Result *hR);
 
 // Allocates / frees a BatchBuffers set (hipMalloc; returns the HIP error).
 hipError_t batch_buffers_alloc(BatchBuffers *bb, size_t capacity);

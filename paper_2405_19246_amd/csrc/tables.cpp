@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cmath>
 
 namespace mmot {
 namespace rt {
@@ -64,8 +65,17 @@ Inst make_inst(int l, int64_t N, double h, double eps)
 }
 
 // Checkpoint bytes for one instance: the largest over the passes it runs.
-size_t scratch_bytes(int l, int64_t N, int precision)
+int64_t tile_min_n(int l)
 {
+    // below this length a sweep on one team (l >= 7) or one wavefront (l <= 6)
+    // is about as fast as the tiled launches and cheaper in total work
+    return l >= WIDE_MINL ? 4096 : 16384;
+}
+
+size_t scratch_bytes(int l, int64_t N, int precision, int flags)
+{
+    int nt = 0, B = 0;
+    if (tile_shape(l, N, flags, &nt, &B)) return tile_scratch_bytes(l, N, nt, B);
     if (l >= WIDE_MINL) return ((size_t)wide_scratch_bytes(l, (long)N) + 255) & ~(size_t)255;
     const int D1 = (1 << (l - 1)) - 1;
     size_t best = 0;
@@ -76,6 +86,16 @@ size_t scratch_bytes(int l, int64_t N, int precision)
         best = std::max(best, (size_t)C * (size_t)D1 * (size_t)elem_bytes(kind));
     }
     return (best + 255) & ~(size_t)255;
+}
+
+int scan_precision(const Inst &I, int precision)
+{
+    if (precision != MMOT_FP32) return MMOT_FP64;
+    // the slowest-decaying state takes g = lambda^(l-1) per position; a scan then
+    // sums about 1 / (1 - g) positions of comparable terms, and FP32 rounding of
+    // that many steps stays below ~1e-7 relative only for short windows
+    const double window = 1.0 / -std::expm1(-(double)(I.l - 1) * I.hoe);
+    return window <= FP32_MAX_WINDOW ? MMOT_FP32 : MMOT_FP64;
 }
 
 bool fast_eligible(const Inst &I, int precision)
@@ -94,6 +114,68 @@ int fast_waves(int l, int64_t N, int kind, int precision)
     const int p = kind == 1 ? 0 : precision;
     const int64_t per = (int64_t)WAVE * fast_v(l, p);
     return (int)std::max<int64_t>(1, (N + per - 1) / per);
+}
+
+namespace {
+
+size_t tr256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+int pow2_ceil(double x)
+{
+    int p = 1;
+    while ((double)p < x && p < (1 << 30)) p <<= 1;
+    return p;
+}
+
+struct Carve {
+    size_t agg, carry, ck_stride, ck, part, total;
+};
+
+Carve carve(int l, int ntile, int B)
+{
+    const size_t D = (size_t)wide_states(l);
+    Carve c;
+    c.agg = tr256((size_t)ntile * 2 * (size_t)l * D * 32);  // elements up to the objective's 32 B
+    c.carry = tr256((size_t)ntile * 2 * D * 32);
+    c.ck_stride = tr256((size_t)wide_scratch_bytes(l, B));
+    c.ck = (size_t)ntile * c.ck_stride;
+    c.part = tr256((size_t)l * (size_t)ntile * sizeof(double));
+    c.total = c.agg + c.carry + c.ck + c.part;
+    return c;
+}
+
+}  // namespace
+
+bool tile_shape(int l, int64_t N, int flags, int *ntile, int *B)
+{
+    const bool force = (flags & F_TILES) != 0;
+    if (!force && N < tile_min_n(l)) return false;
+    int b = force ? pow2_ceil(std::sqrt((double)N)) : pow2_ceil(std::sqrt(8.0 * (double)N));
+    b = std::max(force ? 8 : 64, std::min(b, 4096));
+    *B = b;
+    *ntile = (int)((N + b - 1) / b);
+    return true;
+}
+
+size_t tile_scratch_bytes(int l, int64_t N, int ntile, int B)
+{
+    (void)N;
+    return carve(l, ntile, B).total;
+}
+
+TileInst tile_inst(int l, int ntile, int B, char *scratch)
+{
+    const Carve c = carve(l, ntile, B);
+    TileInst T;
+    std::memset(&T, 0, sizeof T);
+    T.ntile = ntile;
+    T.B = B;
+    T.agg = scratch;
+    T.carry = scratch + c.agg;
+    T.ck = scratch + c.agg + c.carry;
+    T.part = reinterpret_cast<double *>(scratch + c.agg + c.carry + c.ck);
+    T.ck_stride = (long)c.ck_stride;
+    return T;
 }
 
 }  // namespace rt

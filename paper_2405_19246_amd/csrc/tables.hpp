@@ -12,8 +12,27 @@ namespace rt {
 // Descriptor of one problem: shape and the discount tables of every pass kind.
 Inst make_inst(int l, int64_t N, double h, double eps);
 
-// Checkpoint bytes one instance needs in the given precision.
-size_t scratch_bytes(int l, int64_t N, int precision);
+// Scratch bytes one instance needs in the given precision (checkpoints of the
+// one-wavefront and one-team solvers, or every buffer of a tiled solve).
+// flags: F_TILES forces tiles.
+size_t scratch_bytes(int l, int64_t N, int precision, int flags);
+
+// Shortest N that is tiled without F_TILES.
+int64_t tile_min_n(int l);
+
+// Whether an instance is tiled, and its tile count and tile length B (positions).
+bool tile_shape(int l, int64_t N, int flags, int *ntile, int *B);
+
+// Scratch bytes of a tiled solve and its layout inside a scratch block.
+size_t tile_scratch_bytes(int l, int64_t N, int ntile, int B);
+TileInst tile_inst(int l, int ntile, int B, char *scratch);
+
+// Mantissa precision of the scans of an instance solved in `precision`: FP32
+// mode keeps FP32 mantissas where the scan window 1 / (1 - lambda^(l-1)) is at
+// most FP32_MAX_WINDOW positions and takes FP64 mantissas beyond (the same VALU
+// rate on this GPU without packed FP32; only registers and memory double).
+constexpr double FP32_MAX_WINDOW = 64.0;
+int scan_precision(const Inst &I, int precision);
 
 // Whether the register-resident path (fast.hpp) takes an instance: its N fits
 // one workgroup of the sweep and of the FP64 check kernel, and the discount

@@ -148,6 +148,23 @@ __device__ __forceinline__ WConst<L, E> wconst(double hoe, int base, int sign)
     return c;
 }
 
+// a + b p for extended values, the result left unnormalized: the exponents are
+// aligned to the larger one and the mantissas meet in one FMA.  Within one
+// position a state takes at most l - 1 such steps, so its mantissa stays far
+// inside the mantissa type's range until wstep renormalizes it.
+template <typename M>
+__device__ __forceinline__ XF<M> xmac_lazy(XF<M> a, XF<M> b, XF<M> p)
+{
+    const int te = b.e + p.e;
+    const int e = max(a.e, te);
+    return {fma(b.m, xldexp(p.m, te - e), xldexp(a.m, a.e - e)), e};
+}
+__device__ __forceinline__ DXF xmac_lazy(DXF a, DXF b, XF<double> p)
+{
+    return {xmac_lazy(a.v, b.v, p), xmac_lazy(a.w, b.w, p)};
+}
+__device__ __forceinline__ DXF xnorm(DXF x) { return {xnorm(x.v), xnorm(x.w)}; }
+
 // One position of a walk: the gap factor, then the items placed at the position.
 // ph[r] is phi of item r at the position.  BWD: complemented backward states.
 template <int L, typename E, bool BWD, int RG_ = WL<L, E>::RG>
@@ -170,7 +187,7 @@ __device__ __forceinline__ void wstep(E (&A)[RG_], const XF<typename ET<E>::MT> 
                         : (r == 3) ? lmove<3, BWD>(A[i])
                         : (r == 4) ? lmove<4, BWD>(A[i])
                                    : lmove<5, BWD>(A[i]);
-            const E nv = T_::add(A[i], T_::scale(o, p));
+            const E nv = xmac_lazy(A[i], o, p);
             A[i] = esel(upd, nv, A[i]);
         }
     }
@@ -181,9 +198,11 @@ __device__ __forceinline__ void wstep(E (&A)[RG_], const XF<typename ET<E>::MT> 
 #pragma unroll
         for (int i = 0; i < W::RG; ++i) {
             const bool set = (i >> rb) & 1;
-            if (BWD ? !set : set) A[i] = T_::add(A[i], T_::scale(A[i ^ (1 << rb)], p));
+            if (BWD ? !set : set) A[i] = xmac_lazy(A[i], A[i ^ (1 << rb)], p);
         }
     }
+#pragma unroll
+    for (int i = 0; i < W::RG; ++i) A[i] = xnorm(A[i]);
 }
 
 // Sum over the lanes of a team; the total lands in the team's last lane.
@@ -507,6 +526,211 @@ __global__ __launch_bounds__(64) void k_wide_check_all(const Inst *I, Ptrs P, do
     for (int j = 0; j < L; ++j) {
         const WAcc r = wide_pass<L, XF<double>, P_CHECK>(tm, I, j, P.a, P.log_u, nullptr, 0, I->N, nullptr, nullptr);
         if (tm.last) err[j] = r.s;
+    }
+}
+
+}  // namespace mmot
+
+namespace mmot {
+
+// ---- tiles: one instance spread over many teams ------------------------------
+//
+// Positions are cut into tiles of B.  A tile's effect on the forward state is
+// affine in the state it starts from: with S' the summed marginals already
+// placed before the tile and T those placed inside it,
+//     F_end(S) = sum_{S' subset S} F_start(S') Q_{|S'|}(S \ S'),
+// where Q_m(T) is the walk over the tile from the empty placement with every gap
+// discount shifted by m members (g(m + |T|) instead of g(|T|)), because the gap
+// weights only depend on how many members lie to the left.  The backward
+// direction is the mirror image.  So a product runs in three launches:
+//   1. every (tile, m, direction): the walk that gives Q_m   (k_tile_agg)
+//   2. every direction: the carries from tile to tile, in order (k_tile_chain)
+//   3. every tile: the product pass from its true carries      (k_tile_final)
+
+// Walk of one job (tile t, offset m, direction dir) from the empty placement;
+// stores the final state as Q_m of the tile.
+template <int L, typename E>
+__device__ void tile_agg_job(const WTeam<L, E> &tm, const Inst *__restrict__ I, const TileInst &T, const double *a,
+                             int j, int t, int m, int dir)
+{
+    using W = WL<L, E>;
+    using T_ = ET<E>;
+    constexpr int RG = W::RG, CK = W::CK, n = W::n, D = W::D;
+    const long N = I->N;
+    const long p0 = (long)t * T.B, p1 = min(N, p0 + T.B);
+    const int pt = popc(tm.t);
+    E A[RG];
+    if (dir == 0) {
+        const WConst<L, E> c = wconst<L, E>(I->hoe, pt + m, 1);
+#pragma unroll
+        for (int i = 0; i < RG; ++i) A[i] = esel(i * W::TL + tm.t == 0, T_::one(), T_::zero());
+        for (long x0 = p0; x0 < p1; x0 += CK) {
+            const int cnt = (int)min((long)CK, p1 - x0);
+            stage_phi<L, E>(tm, a, N, j, x0, cnt);
+            for (int s = 0; s < cnt; ++s) wstep<L, E, false>(A, tm.ph + s * n, c, tm.t);
+        }
+    } else {
+        const WConst<L, E> c = wconst<L, E>(I->hoe, m + n - pt, -1);
+#pragma unroll
+        for (int i = 0; i < RG; ++i) A[i] = esel(i * W::TL + tm.t == D - 1, T_::one(), T_::zero());
+        const long nb = (p1 - p0 + CK - 1) / CK;
+        for (long b = nb - 1; b >= 0; --b) {
+            const long x0 = p0 + b * CK;
+            const int cnt = (int)min((long)CK, p1 - x0);
+            stage_phi<L, E>(tm, a, N, j, x0, cnt);
+            for (int s = cnt - 1; s >= 0; --s) wstep<L, E, true>(A, tm.ph + s * n, c, tm.t);
+        }
+    }
+    E *q = reinterpret_cast<E *>(T.agg) + (((long)t * 2 + dir) * L + m) * D;
+#pragma unroll
+    for (int i = 0; i < RG; ++i) q[i * W::TL + tm.t] = A[i];
+    team_sync();
+}
+
+// Jobs of the tiled launches: x = instance, y = tile (or direction), z = offset m, w = direction.
+// state_need: the job runs only for instances whose TileTrack.state is this.
+template <int L, typename E>
+__global__ __launch_bounds__(64) void k_tile_agg(const Inst *I, const Ptrs *P, const TileInst *TI, const TileTrack *Tr,
+                                                 const int4 *jobs, int njobs, int j, int state_need)
+{
+    __shared__ __attribute__((aligned(16))) char lds[WShared<L>::TPWMAX * WShared<L>::BYTES];
+    using W = WL<L, E>;
+    const int team = (int)threadIdx.x / W::TL;
+    const int jid = (int)blockIdx.x * W::TPW + team;
+    if (jid >= njobs) return;
+    const int4 jb = jobs[jid];
+    if (Tr && Tr[jb.x].state != state_need) return;
+    const WTeam<L, E> tm = make_team<L, E>(lds, nullptr);
+    tile_agg_job<L, E>(tm, &I[jb.x], TI[jb.x], P[jb.x].a, j, jb.y, jb.z, jb.w);
+}
+
+// Carries from tile to tile in one direction, one workgroup per (instance,
+// direction).  In subset space (forward: S as held; backward: the complement of
+// the index), c_next(S) = sum_{S' subset S} c(S') Q_{|S'|}(S \ S') with c(empty) = 1.
+template <int L, typename E>
+__global__ __launch_bounds__(256) void k_tile_chain(const TileInst *TI, const TileTrack *Tr, const int2 *jobs,
+                                                   int njobs, int state_need)
+{
+    using T_ = ET<E>;
+    constexpr int D = WL<L, E>::D;
+    __shared__ E c[D];
+    const int2 jb = jobs[blockIdx.x];
+    if (Tr && Tr[jb.x].state != state_need) return;
+    const TileInst T = TI[jb.x];
+    const int dir = jb.y;
+    const int tid = threadIdx.x;
+    auto idx = [&](int S) { return dir == 0 ? S : (D - 1) ^ S; };
+    for (int S = tid; S < D; S += blockDim.x) c[S] = esel(S == 0, T_::one(), T_::zero());
+    __syncthreads();
+    E *carry = reinterpret_cast<E *>(T.carry);
+    const E *agg = reinterpret_cast<const E *>(T.agg);
+    for (int s = 0; s < T.ntile; ++s) {
+        const int t = dir == 0 ? s : T.ntile - 1 - s;
+        for (int S = tid; S < D; S += blockDim.x) carry[((long)t * 2 + dir) * D + idx(S)] = c[S];
+        if (s == T.ntile - 1) break;
+        const E *q = agg + ((long)t * 2 + dir) * L * D;
+        E nv[(D + 255) / 256];
+#pragma unroll
+        for (int k = 0; k < (D + 255) / 256; ++k) {
+            const int S = tid + 256 * k;
+            if (S >= D) continue;
+            // S' runs over the subsets of S (S' = S first, the empty set last)
+            E acc = T_::zero();
+            for (int Sp = S;; Sp = (Sp - 1) & S) {
+                acc = T_::add(acc, T_::prod(c[Sp], q[(long)popc(Sp) * D + idx(S ^ Sp)]));
+                if (Sp == 0) break;
+            }
+            nv[k] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < (D + 255) / 256; ++k) {
+            const int S = tid + 256 * k;
+            if (S < D) c[S] = nv[k];
+        }
+        __syncthreads();
+    }
+}
+
+// The product pass of one tile from its carries; the team's per-tile sum goes to
+// part[j][t].
+template <int L, typename E, int MODE>
+__global__ __launch_bounds__(64) void k_tile_final(const Inst *I, const Ptrs *P, const TileInst *TI,
+                                                   const TileTrack *Tr, const int2 *jobs, int njobs, int j,
+                                                   int state_need)
+{
+    __shared__ __attribute__((aligned(16))) char lds[WShared<L>::TPWMAX * WShared<L>::BYTES];
+    using W = WL<L, E>;
+    constexpr int D = W::D;
+    const int team = (int)threadIdx.x / W::TL;
+    const int jid = (int)blockIdx.x * W::TPW + team;
+    if (jid >= njobs) return;
+    const int2 jb = jobs[jid];
+    if (Tr && Tr[jb.x].state != state_need) return;
+    const TileInst T = TI[jb.x];
+    const Inst *In = &I[jb.x];
+    const Ptrs Pp = P[jb.x];
+    const int t = jb.y;
+    const long p0 = (long)t * T.B, p1 = min(In->N, p0 + T.B);
+    const WTeam<L, E> tm = make_team<L, E>(lds, T.ck + (long)t * T.ck_stride);
+    const E *carry = reinterpret_cast<const E *>(T.carry);
+    const WAcc r = wide_pass<L, E, MODE>(tm, In, j, Pp.a, Pp.log_u, Pp.out, p0, p1, carry + ((long)t * 2 + 0) * D,
+                                         carry + ((long)t * 2 + 1) * D);
+    if (tm.last) T.part[(long)j * T.ntile + t] = (MODE == P_OBJECTIVE) ? In->h * xto_double(r.x) : r.s;
+}
+
+// After the update passes of a sweep: the estimate, then whether a residual
+// check is due (same rule as the one-team solver).  One thread per instance.
+template <int L>
+__global__ void k_tile_ctrl_sweep(const Ptrs *P, const TileInst *TI, TileTrack *Tr, int count, RunOpts o)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    TileTrack &R = Tr[i];
+    if (R.state != TS_SWEEP) return;
+    const TileInst T = TI[i];
+    double est = 0.0;
+    for (int j = 0; j < L - 1; ++j)
+        for (int t = 0; t < T.ntile; ++t) est += T.part[(long)j * T.ntile + t];
+    const long itr_max = P[i].itr_cap > 0 ? P[i].itr_cap : o.itr_max;
+    const int flags = o.flags | P[i].flags;
+    R.it += 1;
+    R.est = est;
+    if (!(est == est)) {
+        R.state = TS_DONE;
+        R.status = ST_NUMERIC;
+        return;
+    }
+    const bool chk = !(flags & F_NO_CHECK) && ((o.check_every > 0 && R.it % o.check_every == 0) ||
+                                                R.it >= itr_max || (o.tol >= 0.0 && est <= o.tol * R.f));
+    if (chk) R.state = TS_CHECK;
+    else if (R.it >= itr_max) R.state = TS_DONE;
+}
+
+// After the check passes: the FP64 residual and the stopping decision.
+template <int L>
+__global__ void k_tile_ctrl_check(const Ptrs *P, const TileInst *TI, TileTrack *Tr, int count, RunOpts o)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    TileTrack &R = Tr[i];
+    if (R.state != TS_CHECK) return;
+    const TileInst T = TI[i];
+    double res = 0.0;
+    for (int j = 0; j < L - 1; ++j)
+        for (int t = 0; t < T.ntile; ++t) res += T.part[(long)j * T.ntile + t];
+    const long itr_max = P[i].itr_cap > 0 ? P[i].itr_cap : o.itr_max;
+    R.res = res;
+    R.checked = 1;
+    if (!(res == res)) {
+        R.state = TS_DONE;
+        R.status = ST_NUMERIC;
+    } else if (res <= o.tol || R.it >= itr_max) {
+        R.state = TS_DONE;
+        R.status = ST_OK;
+    } else {
+        if (o.tol >= 0.0 && R.est <= o.tol * R.f) R.f *= 0.5;
+        R.state = TS_SWEEP;
     }
 }
 

@@ -1,0 +1,171 @@
+"""Tiled solves through the C ABI against the oracle: an instance's positions are
+cut into tiles that run on many teams at once (k_tile_agg, k_tile_chain,
+k_tile_final and the controllers).
+
+MMOT_FLAG_TILES forces tiles at small N (tile length the power of two at or
+above sqrt(N), at least 8), so every case below crosses several tiles and ends
+in a ragged one; the long cases are tiled without the flag (N >= 16384 for
+l <= 6, N >= 4096 for l >= 7).
+
+Tolerances: FP64 1e-12 relative (products pointwise, potentials gauge-fixed,
+objective); FP32 solves certified by the oracle's FP64 marginal errors.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import log_rel_err, potentials_err, say, to_dev
+from oracle import fastcheck
+from paper_2405_19246_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FORCED = [(2, 50), (3, 70), (4, 130), (5, 100), (6, 64), (7, 70), (8, 40), (9, 30), (10, 19)]
+
+
+def _mmot():
+    from paper_2405_19246_amd import mmot
+    return mmot
+
+
+def _rand_potentials(l, N, seed, scale=3.0):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=(l, N)) * scale
+    if N > 2:
+        a[0, 1] = -np.inf
+        a[l - 1, N - 1] = -np.inf
+    return a
+
+
+@pytest.mark.parametrize("l,N", FORCED)
+def test_tiled_product_fp64_matches_oracle(l, N):
+    mmot = _mmot()
+    h, eps = inputs.grid_step(N), 0.05
+    a = _rand_potentials(l, N, 31 * l + N)
+    plan = mmot.Plan(l, N, h, eps, precision=mmot.FP64, tiles=True)
+    ta = to_dev(a)
+    for j in range(l):
+        say("tiled product fp64 l=%d N=%d j=%d" % (l, N, j))
+        got = plan.marginal_product(j, ta).cpu().numpy()
+        ref = fastcheck.marginal_product_log(a, j, h, eps)
+        assert log_rel_err(got, ref) < FP64_TOL, (l, N, j, log_rel_err(got, ref))
+
+
+@pytest.mark.parametrize("l,N", [(3, 70), (7, 70)])
+def test_tiled_product_fp32_error_is_small(l, N):
+    mmot = _mmot()
+    h, eps = inputs.grid_step(N), 0.02
+    a = _rand_potentials(l, N, 7 * l + N, scale=10.0)
+    plan = mmot.Plan(l, N, h, eps, precision=mmot.FP32, tiles=True)
+    worst = 0.0
+    for j in range(l):
+        say("tiled product fp32 l=%d N=%d j=%d" % (l, N, j))
+        got = plan.marginal_product(j, to_dev(a)).cpu().numpy()
+        worst = max(worst, log_rel_err(got, fastcheck.marginal_product_log(a, j, h, eps)))
+    print("tiled fp32 product l=%d N=%d: max relative error %.3e" % (l, N, worst))
+    assert worst < 2e-5
+
+
+@pytest.mark.parametrize("l,N", [(3, 70), (4, 50), (6, 40), (8, 30), (10, 19)])
+def test_tiled_solve_fp64_fixed_sweeps_match_oracle(l, N):
+    mmot = _mmot()
+    u = inputs.marginals(l, N, K=3, master_seed=41, instance=N)
+    h, eps = inputs.grid_step(N), 0.05
+    say("tiled solve fp64 l=%d N=%d, 15 sweeps" % (l, N))
+    plan = mmot.Plan(l, N, h, eps, precision=mmot.FP64, tol=-1.0, itr_max=15, check_every=0, tiles=True)
+    log_phi, res = plan.solve(to_dev(np.log(u)))
+    ref = fastcheck.sinkhorn(u, h, eps, itmax=15, check_every=15)
+    assert res["iters"] == 15
+    assert potentials_err(log_phi.cpu().numpy(), ref["log_phi"]) < FP64_TOL
+    assert abs(res["W"] - ref["W"]) <= FP64_TOL * abs(ref["W"])
+    assert abs(res["marg_err"] - ref["res"]) <= 1e-10 * max(ref["res"], 1e-300)
+
+
+@pytest.mark.parametrize("l,N", [(4, 45), (9, 21)])
+def test_tiled_objective_and_marginal_errors(l, N):
+    mmot = _mmot()
+    h, eps = inputs.grid_step(N), 0.07
+    a = _rand_potentials(l, N, 3 * l + N, scale=2.0)
+    u = inputs.marginals(l, N, K=2, master_seed=5, instance=N)
+    plan = mmot.Plan(l, N, h, eps, precision=mmot.FP64, tiles=True)
+    say("tiled objective l=%d N=%d" % (l, N))
+    W = plan.objective(to_dev(a))
+    Wr = fastcheck.objective(a, h, eps)
+    assert abs(W - Wr) <= FP64_TOL * abs(Wr), (W, Wr)
+    say("tiled marginal errors l=%d N=%d" % (l, N))
+    err = plan.marginal_errors(to_dev(np.log(u)), to_dev(a))
+    np.testing.assert_allclose(err, fastcheck.marginal_errors(u, a, h, eps), rtol=1e-10)
+
+
+@pytest.mark.parametrize("l,N", [(3, 65536), (4, 100000), (6, 65536)])
+def test_long_product_fp64_eps_1e3_matches_oracle(l, N):
+    # tiled without the flag; eps = 1e-3 and potentials of the size a solve reaches
+    mmot = _mmot()
+    h, eps = inputs.grid_step(N), 1e-3
+    u = inputs.marginals(l, N, K=3, master_seed=3, instance=l)
+    rng = np.random.default_rng(l)
+    a = np.log(u) + rng.normal(size=(l, N)) * 2.0
+    plan = mmot.Plan(l, N, h, eps, precision=mmot.FP64)
+    ta = to_dev(a)
+    for j in (0, l - 1):
+        say("long product fp64 l=%d N=%d j=%d" % (l, N, j))
+        got = plan.marginal_product(j, ta).cpu().numpy()
+        ref = fastcheck.marginal_product_log(a, j, h, eps)
+        assert log_rel_err(got, ref) < FP64_TOL, (l, N, j, log_rel_err(got, ref))
+
+
+def test_long_product_fp64_l10_matches_oracle():
+    # the l = 10, eps = 1e-3 shape at N = 6000 (tiled: N >= 4096)
+    mmot = _mmot()
+    l, N = 10, 6000
+    h, eps = inputs.grid_step(N), 1e-3
+    u = inputs.marginals(l, N, K=5, master_seed=0, instance=0, floor=0.0, uniform_frac=0.1)
+    a = np.log(u) + np.random.default_rng(10).normal(size=(l, N))
+    plan = mmot.Plan(l, N, h, eps, precision=mmot.FP64)
+    say("long product fp64 l=10 N=6000 j=4")
+    got = plan.marginal_product(4, to_dev(a)).cpu().numpy()
+    ref = fastcheck.marginal_product_log(a, 4, h, eps)
+    assert log_rel_err(got, ref) < FP64_TOL, log_rel_err(got, ref)
+
+
+def test_long_sweeps_fp64_match_oracle():
+    # three Gauss-Seidel sweeps of a tiled l = 4 instance at N = 20000, eps = 1e-3
+    mmot = _mmot()
+    l, N = 4, 20000
+    h, eps = inputs.grid_step(N), 1e-3
+    u = inputs.marginals(l, N, K=3, master_seed=2, instance=0)
+    ta = to_dev(np.full((l, N), -np.log(N)))
+    plan = mmot.Plan(l, N, h, eps, precision=mmot.FP64)
+    say("long sweeps fp64 l=4 N=20000")
+    err = plan.sinkhorn_iter(to_dev(np.log(u)), ta, 3)
+    ref = fastcheck.sinkhorn(u, h, eps, itmax=3, check_every=3)
+    assert potentials_err(ta.cpu().numpy(), ref["log_phi"]) < FP64_TOL
+    assert abs(err - ref["res"]) <= 1e-10 * ref["res"]
+
+
+def test_tiled_batch_fp32_certified():
+    # tiled and untiled instances in one batch, FP32 mode to Res <= 1e-6, each
+    # certified by the oracle's FP64 marginal errors (the long-window instances
+    # run on FP64 mantissas: their scan windows exceed 64 positions)
+    import time
+    mmot = _mmot()
+    cases = [(3, 20000, 0.05), (4, 17000, 0.1), (7, 4500, 0.1), (3, 300, 0.05), (8, 200, 0.1)]
+    insts = []
+    for s, (l, N, eps) in enumerate(cases):
+        u = inputs.marginals(l, N, K=3, master_seed=44, instance=s)
+        insts.append(dict(l=l, N=N, h=inputs.grid_step(N), eps=eps, u=u, log_u=to_dev(np.log(u)),
+                          log_phi=to_dev(np.zeros((l, N)))))
+    say("tiled batch fp32 to 1e-6, itr_max 4000")
+    t0 = time.perf_counter()
+    res = mmot.solve_batch(insts, precision=mmot.FP32, tol=1e-6, itr_max=4000, check_every=0)
+    print("batch of %d: %.2f s" % (len(insts), time.perf_counter() - t0), flush=True)
+    for d, r in zip(insts, res):
+        err = fastcheck.marginal_errors(d["u"], d["log_phi"].cpu().numpy(), d["h"], d["eps"])
+        print("l=%d N=%d eps=%g status=%d sweeps=%d Res=%.3e certified Res=%.3e" %
+              (d["l"], d["N"], d["eps"], r["status"], r["iters"], r["marg_err"], err[:-1].sum()), flush=True)
+    for d, r in zip(insts, res):
+        assert r["status"] == 0, (d["l"], d["N"], r)
+        err = fastcheck.marginal_errors(d["u"], d["log_phi"].cpu().numpy(), d["h"], d["eps"])
+        assert err[:-1].sum() <= 1e-6, (d["l"], d["N"], err)
+        ref = fastcheck.objective(d["log_phi"].cpu().numpy(), d["h"], d["eps"])
+        assert abs(r["W"] - ref) <= 1e-10 * abs(ref), (d["l"], d["N"])
