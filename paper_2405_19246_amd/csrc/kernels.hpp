@@ -102,13 +102,7 @@ __device__ void solve_dispatch(const Inst *I, const Ptrs P, const RunOpts o, Res
         case 4: solve_one<4, M>(I, P, o, R, lane); break;
         case 5: solve_one<5, M>(I, P, o, R, lane); break;
         case 6: solve_one<6, M>(I, P, o, R, lane); break;
-#if MMOT_BUILD_MAXL >= 7
-        case 7: solve_one<7, M>(I, P, o, R, lane); break;
-#endif
-#if MMOT_BUILD_MAXL >= 8
-        case 8: solve_one<8, M>(I, P, o, R, lane); break;
-#endif
-        default: break;
+        default: break;  // l >= 7 runs on the team layout (wide.hpp)
     }
 }
 
