@@ -138,6 +138,23 @@ int mmot_sinkhorn_iter(const mmot_plan_t *plan, const double *log_u, double *log
  */
 int mmot_solve(const mmot_plan_t *plan, const double *log_u, double *log_phi, mmot_result *res);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the product
+ * of mmot_marginal_product for the problem p, without a plan.  Its workspace
+ * (the problem descriptor and the scan checkpoints) is a fixed device array of
+ * MMOT_NOALLOC_BYTES per GPU, set up on the first call on each device and held
+ * until the process ends; no call allocates.  Problems whose workspace would
+ * exceed it are rejected with MMOT_ERR_INVALID before any device work.  Every
+ * call on one GPU shares that GPU's workspace: calls that overlap on one GPU
+ * (other streams or threads) race.  Runs the single-pass kernels (no tiles)
+ * in p->precision on hip_stream (NULL = default).  j, log_phi, log_J as in
+ * mmot_marginal_product.
+ */
+#define MMOT_NOALLOC_BYTES (16u << 20)
+int mmot_marginal_product_noalloc(const mmot_problem *p, int32_t j, const double *log_phi, double *log_J,
+                                  void *hip_stream);
+
 /* W_eps = <C, T> of the plan with potentials log_phi (Sec. 2 Eq. mmot distance;
  * Sec. 3.2 FTVP-2 for l = 3), FP64.  W: host, synchronises. */
 int mmot_objective(const mmot_plan_t *plan, const double *log_phi, double *W);

@@ -47,6 +47,7 @@ def _units():
     units.append((os.path.join(HERE, "api.cpp"), "api.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "serve.cpp"), "serve.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "tile.cpp"), "tile.o", ["-x", "hip"]))
+    units.append((os.path.join(HERE, "noalloc.cpp"), "noalloc.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "tables.cpp"), "tables.o", []))
     return units
 

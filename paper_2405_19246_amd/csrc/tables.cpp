@@ -76,6 +76,11 @@ size_t scratch_bytes(int l, int64_t N, int precision, int flags)
 {
     int nt = 0, B = 0;
     if (tile_shape(l, N, flags, &nt, &B)) return tile_scratch_bytes(l, N, nt, B);
+    return pass_scratch_bytes(l, N, precision);
+}
+
+size_t pass_scratch_bytes(int l, int64_t N, int precision)
+{
     if (l >= WIDE_MINL) return ((size_t)wide_scratch_bytes(l, (long)N) + 255) & ~(size_t)255;
     const int D1 = (1 << (l - 1)) - 1;
     size_t best = 0;

@@ -17,6 +17,9 @@ Inst make_inst(int l, int64_t N, double h, double eps);
 // flags: F_TILES forces tiles.
 size_t scratch_bytes(int l, int64_t N, int precision, int flags);
 
+// Checkpoint bytes of one untiled product / check / objective pass.
+size_t pass_scratch_bytes(int l, int64_t N, int precision);
+
 // Shortest N that is tiled without F_TILES.
 int64_t tile_min_n(int l);
 

@@ -74,7 +74,7 @@ REQUEST_FN = ctypes.CFUNCTYPE(ctypes.c_int, _c_p, _c_i64, ctypes.POINTER(Request
 EXPORTS = ["mmot_plan", "mmot_plan_footprint", "mmot_plan_destroy", "mmot_marginal_product", "mmot_sinkhorn_iter",
            "mmot_solve", "mmot_objective", "mmot_marginal_errors", "mmot_solve_batch", "mmot_serve_start",
            "mmot_serve_submit", "mmot_serve_poll", "mmot_serve_stop", "mmot_serve", "mmot_last_batch_kernel_ms",
-           "mmot_last_batch_timing", "mmot_last_error"]
+           "mmot_last_batch_timing", "mmot_marginal_product_noalloc", "mmot_last_error"]
 
 
 class MmotError(RuntimeError):
@@ -117,6 +117,7 @@ def lib() -> ctypes.CDLL:
         L.mmot_serve.argtypes = [PP(ServeCfg), REQUEST_FN, _c_p, PP(ServeStats), PP(RequestRecord), _c_i64]
         L.mmot_last_batch_kernel_ms.argtypes = [PP(_c_d)]
         L.mmot_last_batch_timing.argtypes = [PP(BatchTiming)]
+        L.mmot_marginal_product_noalloc.argtypes = [PP(Problem), _c_i32, _c_p, _c_p, _c_p]
         L.mmot_last_error.argtypes = []
         L.mmot_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
@@ -225,6 +226,21 @@ class Plan:
         err = (_c_d * self.l)()
         _check(lib().mmot_marginal_errors(self._h, _c_p(pu), _c_p(pa), err))
         return np.array(list(err))
+
+
+NOALLOC_BYTES = 16 << 20
+
+
+def marginal_product_noalloc(l: int, N: int, h: float, eps: float, j: int, log_phi, out, precision: int = FP64,
+                             stream=None):
+    """mmot_marginal_product_noalloc: the product into the caller's out tensor [N], using the library's
+    fixed per-GPU workspace (no allocation, no plan)."""
+    pa = _dev_f64(log_phi, (int(l), int(N)), "log_phi")
+    po = _dev_f64(out, (int(N),), "out")
+    p = Problem(int(l), int(N), float(h), float(eps), int(precision))
+    _check(lib().mmot_marginal_product_noalloc(ctypes.byref(p), int(j), _c_p(pa), _c_p(po),
+                                               _c_p(_stream_handle(stream))))
+    return out
 
 
 def last_batch_kernel_ms() -> float:

@@ -85,3 +85,17 @@ def test_null_plan_calls_are_invalid():
     assert L.mmot_solve(None, None, None, None) == -1
     assert L.mmot_plan_destroy(None) == 0
     assert L.mmot_serve_stop(None) == 0
+
+
+def test_noalloc_product_checks_before_device_work():
+    # size and argument checks of the no-allocation entry point need no GPU
+    mmot = _lib()
+    L = mmot.lib()
+    p = mmot.Problem(10, 1000000, 1e-6, 0.01, 0)
+    dummy = ctypes.c_void_p(16)
+    assert L.mmot_marginal_product_noalloc(ctypes.byref(p), 0, dummy, dummy, None) == -1
+    assert "workspace" in mmot.last_error()
+    p = mmot.Problem(4, 100, 0.01, 0.01, 0)
+    assert L.mmot_marginal_product_noalloc(ctypes.byref(p), 4, dummy, dummy, None) == -1
+    assert L.mmot_marginal_product_noalloc(ctypes.byref(p), 0, None, dummy, None) == -1
+    assert L.mmot_marginal_product_noalloc(None, 0, dummy, dummy, None) == -1
