@@ -46,6 +46,7 @@ extern "C" {
 #define MMOT_ERR_UNSUPPORTED (-5) /* valid request this build does not implement */
 #define MMOT_ERR_HIP (-6)         /* a HIP runtime call failed (message names it) */
 #define MMOT_ERR_STATE (-7)       /* server stopped, unknown ticket, or call out of order */
+#define MMOT_ERR_INTERNAL (-8)    /* unexpected failure inside the library (host resources; message names it) */
 
 #define MMOT_MAX_L 10             /* largest number of marginals per problem */
 
@@ -60,6 +61,13 @@ typedef struct {
     double eps;
     int32_t precision; /* MMOT_FP64 or MMOT_FP32 */
 } mmot_problem;
+
+/* Marginals passed to the solving calls (mmot_sinkhorn_iter, mmot_solve,
+ * mmot_solve_batch, mmot_serve_submit) must be probability vectors: no NaN,
+ * no negative mass (in log form: no NaN and no +inf), and each row's mass
+ * sum_i exp(log_u[q][i]) within 1e-12 of 1 in FP64; otherwise the call returns
+ * MMOT_ERR_INVALID naming the instance and row, before any sweep runs (the
+ * device-pointer calls check on the device first, then synchronise). */
 
 /* Stopping rule of Alg. 1: stop after itr_max sweeps or once Res <= tol, where
  * Res = sum_{j < l} || phi_j * (K x_{q != j} phi_q) - u_j ||_1 (the last marginal
@@ -266,7 +274,8 @@ int mmot_serve_stop(mmot_server_t *srv);
 /* Summary of a blocking serving run. */
 typedef struct {
     int64_t completed;
-    int64_t rejected;          /* footprint above the whole budget */
+    int64_t rejected;          /* refused at submission: footprint above the whole budget, or a request
+                                  mmot_serve_submit rejects (e.g. l > MMOT_MAX_L); the rest are served */
     double wall_seconds;
     double p50_latency;        /* seconds, submit to done */
     double p99_latency;

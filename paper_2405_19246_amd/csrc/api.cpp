@@ -27,6 +27,19 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+int guard_fail()
+{
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        return fail(MMOT_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(MMOT_ERR_INTERNAL, std::string("internal error: ") + e.what());
+    } catch (...) {
+        return fail(MMOT_ERR_INTERNAL, "internal error");
+    }
+}
+
 #define HIPCHK(call)                                                                                   \
     do {                                                                                               \
         hipError_t e_ = (call);                                                                        \
@@ -86,65 +99,77 @@ const char *mmot_last_error(void) { return g_err.c_str(); }
 
 int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_plan_t **out)
 {
-    if (!p || !out) return fail(MMOT_ERR_INVALID, "problem or out is NULL");
-    *out = nullptr;
-    int rc = check_shape(p->l, p->N, p->h, p->eps);
-    if (rc) return rc;
-    if (p->precision != MMOT_FP64 && p->precision != MMOT_FP32)
-        return fail(MMOT_ERR_INVALID, "precision must be MMOT_FP64 or MMOT_FP32");
-    mmot_opts oo = {1e-8, 1000, 10, 0};
-    if (o) {
-        rc = check_opts(o);
+    try {
+        if (!p || !out) return fail(MMOT_ERR_INVALID, "problem or out is NULL");
+        *out = nullptr;
+        int rc = check_shape(p->l, p->N, p->h, p->eps);
         if (rc) return rc;
-        oo = *o;
+        if (p->precision != MMOT_FP64 && p->precision != MMOT_FP32)
+            return fail(MMOT_ERR_INVALID, "precision must be MMOT_FP64 or MMOT_FP32");
+        mmot_opts oo = {1e-8, 1000, 10, 0};
+        if (o) {
+            rc = check_opts(o);
+            if (rc) return rc;
+            oo = *o;
+        }
+        mmot_plan_t *pl = new mmot_plan_t();
+        pl->p = *p;
+        pl->o = oo;
+        pl->s = (hipStream_t)hip_stream;
+        const Inst I = make_inst(p->l, p->N, p->h, p->eps);
+        pl->hI = I;
+        pl->tiled = tile_shape(p->l, p->N, plan_flags(oo), &pl->ntile, &pl->B);
+        pl->scratch_size = scratch_bytes(p->l, p->N, p->precision, plan_flags(oo));
+        hipError_t e = hipMalloc((void **)&pl->dI, sizeof(Inst));
+        if (e == hipSuccess) e = hipMalloc(&pl->scratch, std::max<size_t>(pl->scratch_size, 256));
+        if (e == hipSuccess) e = hipMalloc((void **)&pl->dR, sizeof(Result));
+        if (e == hipSuccess) e = hipMalloc((void **)&pl->dtmp, sizeof(double) * MAXL);
+        if (e == hipSuccess) e = batch_buffers_alloc(&pl->bb, 1);
+        if (e == hipSuccess) e = hipMemcpy(pl->dI, &I, sizeof(Inst), hipMemcpyHostToDevice);
+        if (e == hipSuccess && pl->tiled) {
+            pl->hTI = tile_inst(p->l, pl->ntile, pl->B, reinterpret_cast<char *>(pl->scratch));
+            e = hipMemcpy(pl->bb.dTI, &pl->hTI, sizeof(TileInst), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(pl->bb.dI, &I, sizeof(Inst), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            mmot_plan_destroy(pl);
+            return fail(e == hipErrorOutOfMemory ? MMOT_ERR_NOMEM : MMOT_ERR_HIP,
+                        std::string("plan allocation: ") + hipGetErrorString(e));
+        }
+        *out = pl;
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
     }
-    mmot_plan_t *pl = new mmot_plan_t();
-    pl->p = *p;
-    pl->o = oo;
-    pl->s = (hipStream_t)hip_stream;
-    const Inst I = make_inst(p->l, p->N, p->h, p->eps);
-    pl->hI = I;
-    pl->tiled = tile_shape(p->l, p->N, plan_flags(oo), &pl->ntile, &pl->B);
-    pl->scratch_size = scratch_bytes(p->l, p->N, p->precision, plan_flags(oo));
-    hipError_t e = hipMalloc((void **)&pl->dI, sizeof(Inst));
-    if (e == hipSuccess) e = hipMalloc(&pl->scratch, std::max<size_t>(pl->scratch_size, 256));
-    if (e == hipSuccess) e = hipMalloc((void **)&pl->dR, sizeof(Result));
-    if (e == hipSuccess) e = hipMalloc((void **)&pl->dtmp, sizeof(double) * MAXL);
-    if (e == hipSuccess) e = batch_buffers_alloc(&pl->bb, 1);
-    if (e == hipSuccess) e = hipMemcpy(pl->dI, &I, sizeof(Inst), hipMemcpyHostToDevice);
-    if (e == hipSuccess && pl->tiled) {
-        pl->hTI = tile_inst(p->l, pl->ntile, pl->B, reinterpret_cast<char *>(pl->scratch));
-        e = hipMemcpy(pl->bb.dTI, &pl->hTI, sizeof(TileInst), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(pl->bb.dI, &I, sizeof(Inst), hipMemcpyHostToDevice);
-    }
-    if (e != hipSuccess) {
-        mmot_plan_destroy(pl);
-        return fail(e == hipErrorOutOfMemory ? MMOT_ERR_NOMEM : MMOT_ERR_HIP,
-                    std::string("plan allocation: ") + hipGetErrorString(e));
-    }
-    *out = pl;
-    return MMOT_OK;
 }
 
 int mmot_plan_footprint(const mmot_plan_t *pl, size_t *device_bytes)
 {
-    if (!pl || !device_bytes) return fail(MMOT_ERR_INVALID, "NULL argument");
-    *device_bytes = 2 * sizeof(Inst) + pl->scratch_size + 2 * sizeof(Result) + sizeof(double) * MAXL +
-                    sizeof(Ptrs) + 3 * sizeof(int) + sizeof(Track) +
-                    2 * sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N;
-    return MMOT_OK;
+    try {
+        if (!pl || !device_bytes) return fail(MMOT_ERR_INVALID, "NULL argument");
+        *device_bytes = 2 * sizeof(Inst) + pl->scratch_size + 2 * sizeof(Result) + sizeof(double) * MAXL +
+                        sizeof(Ptrs) + 3 * sizeof(int) + sizeof(Track) +
+                        2 * sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N;
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
+    }
 }
 
 int mmot_plan_destroy(mmot_plan_t *pl)
 {
-    if (!pl) return MMOT_OK;
-    if (pl->dI) (void)hipFree(pl->dI);
-    batch_buffers_free(&pl->bb);
-    if (pl->scratch) (void)hipFree(pl->scratch);
-    if (pl->dR) (void)hipFree(pl->dR);
-    if (pl->dtmp) (void)hipFree(pl->dtmp);
-    delete pl;
-    return MMOT_OK;
+    try {
+        if (!pl) return MMOT_OK;
+        if (pl->dI) (void)hipFree(pl->dI);
+        batch_buffers_free(&pl->bb);
+        if (pl->scratch) (void)hipFree(pl->scratch);
+        if (pl->dR) (void)hipFree(pl->dR);
+        if (pl->dtmp) (void)hipFree(pl->dtmp);
+        delete pl;
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
+    }
 }
 
 // One tiled pass (product, FP64 errors of every marginal, or objective) of a
@@ -185,26 +210,34 @@ static int plan_tile_sums(const mmot_plan_t *pl, int j0, int j1, double *sums)
 
 int mmot_marginal_product(const mmot_plan_t *pl, int32_t j, const double *log_phi, double *log_J)
 {
-    if (!pl || !log_phi || !log_J) return fail(MMOT_ERR_INVALID, "NULL argument");
-    if (j < 0 || j >= pl->p.l) return fail(MMOT_ERR_INVALID, "j out of range");
-    if (pl->tiled) return plan_tile_pass(pl, P_PRODUCT, j, nullptr, log_phi, log_J);
-    Ptrs P = {nullptr, const_cast<double *>(log_phi), log_J, pl->scratch, 0, 0, 0, 0};
-    HIPCHK(launch_pass(pl->p.l, pl->p.precision, 0, pl->dI, P, j, nullptr, pl->s));
-    return MMOT_OK;
+    try {
+        if (!pl || !log_phi || !log_J) return fail(MMOT_ERR_INVALID, "NULL argument");
+        if (j < 0 || j >= pl->p.l) return fail(MMOT_ERR_INVALID, "j out of range");
+        if (pl->tiled) return plan_tile_pass(pl, P_PRODUCT, j, nullptr, log_phi, log_J);
+        Ptrs P = {nullptr, const_cast<double *>(log_phi), log_J, pl->scratch, 0, 0, 0, 0};
+        HIPCHK(launch_pass(pl->p.l, pl->p.precision, 0, pl->dI, P, j, nullptr, pl->s));
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
+    }
 }
 
 int mmot_marginal_errors(const mmot_plan_t *pl, const double *log_u, const double *log_phi, double *err)
 {
-    if (!pl || !log_u || !log_phi || !err) return fail(MMOT_ERR_INVALID, "NULL argument");
-    if (pl->tiled) {
-        const int rc = plan_tile_pass(pl, P_CHECK, 0, log_u, log_phi, nullptr);
-        return rc ? rc : plan_tile_sums(pl, 0, pl->p.l, err);
+    try {
+        if (!pl || !log_u || !log_phi || !err) return fail(MMOT_ERR_INVALID, "NULL argument");
+        if (pl->tiled) {
+            const int rc = plan_tile_pass(pl, P_CHECK, 0, log_u, log_phi, nullptr);
+            return rc ? rc : plan_tile_sums(pl, 0, pl->p.l, err);
+        }
+        Ptrs P = {log_u, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
+        HIPCHK(launch_pass(pl->p.l, MMOT_FP64, 2, pl->dI, P, 0, pl->dtmp, pl->s));
+        HIPCHK(hipMemcpyAsync(err, pl->dtmp, sizeof(double) * pl->p.l, hipMemcpyDeviceToHost, pl->s));
+        HIPCHK(hipStreamSynchronize(pl->s));
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
     }
-    Ptrs P = {log_u, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
-    HIPCHK(launch_pass(pl->p.l, MMOT_FP64, 2, pl->dI, P, 0, pl->dtmp, pl->s));
-    HIPCHK(hipMemcpyAsync(err, pl->dtmp, sizeof(double) * pl->p.l, hipMemcpyDeviceToHost, pl->s));
-    HIPCHK(hipStreamSynchronize(pl->s));
-    return MMOT_OK;
 }
 
 static int plan_path(const mmot_plan_t *pl)
@@ -215,62 +248,74 @@ static int plan_path(const mmot_plan_t *pl)
 int mmot_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_phi, int64_t n_sweeps,
                        double *marg_err)
 {
-    if (!pl || !log_u || !log_phi) return fail(MMOT_ERR_INVALID, "NULL argument");
-    if (n_sweeps < 0) return fail(MMOT_ERR_INVALID, "n_sweeps must be >= 0");
-    if (n_sweeps > 0) {
-        RunOpts o = {-1.0, n_sweeps, 0, F_WARM | F_NO_OBJ | (marg_err ? 0 : F_NO_CHECK) | plan_path(pl)};
-        Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, F_WARM, 0};
-        Result R;
-        int rc = batch_launch(&pl->hI, &P, 1, pl->p.precision, o, pl->s, &R, &pl->bb);
-        if (rc) return rc;
+    try {
+        if (!pl || !log_u || !log_phi) return fail(MMOT_ERR_INVALID, "NULL argument");
+        if (n_sweeps < 0) return fail(MMOT_ERR_INVALID, "n_sweeps must be >= 0");
+        if (n_sweeps > 0) {
+            RunOpts o = {-1.0, n_sweeps, 0, F_WARM | F_NO_OBJ | F_VALIDATE | (marg_err ? 0 : F_NO_CHECK) | plan_path(pl)};
+            Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, F_WARM, 0};
+            Result R;
+            int rc = batch_launch(&pl->hI, &P, 1, pl->p.precision, o, pl->s, &R, &pl->bb);
+            if (rc) return rc;
+            if (!marg_err) return MMOT_OK;
+            *marg_err = R.marg_err;
+            if (R.status == MMOT_ERR_NUMERIC || !std::isfinite(R.marg_err)) return fail(MMOT_ERR_NUMERIC, "non-finite residual");
+            return MMOT_OK;
+        }
         if (!marg_err) return MMOT_OK;
-        *marg_err = R.marg_err;
-        if (R.status == MMOT_ERR_NUMERIC || !std::isfinite(R.marg_err)) return fail(MMOT_ERR_NUMERIC, "non-finite residual");
-        return MMOT_OK;
+        double err[MAXL];
+        int rc = mmot_marginal_errors(pl, log_u, log_phi, err);
+        if (rc) return rc;
+        double r = 0.0;
+        for (int j = 0; j < pl->p.l - 1; ++j) r += err[j];
+        *marg_err = r;
+        return std::isfinite(r) ? MMOT_OK : fail(MMOT_ERR_NUMERIC, "non-finite residual");
+    } catch (...) {
+        return guard_fail();
     }
-    if (!marg_err) return MMOT_OK;
-    double err[MAXL];
-    int rc = mmot_marginal_errors(pl, log_u, log_phi, err);
-    if (rc) return rc;
-    double r = 0.0;
-    for (int j = 0; j < pl->p.l - 1; ++j) r += err[j];
-    *marg_err = r;
-    return std::isfinite(r) ? MMOT_OK : fail(MMOT_ERR_NUMERIC, "non-finite residual");
 }
 
 int mmot_solve(const mmot_plan_t *pl, const double *log_u, double *log_phi, mmot_result *res)
 {
-    if (!pl || !log_u || !log_phi || !res) return fail(MMOT_ERR_INVALID, "NULL argument");
-    const int warm = (pl->o.flags & MMOT_FLAG_WARM_START) ? F_WARM : 0;
-    RunOpts o = {pl->o.tol, pl->o.itr_max, pl->o.check_every, plan_path(pl)};
-    Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, warm, 0};
-    Result R;
-    int rc = batch_launch(&pl->hI, &P, 1, pl->p.precision, o, pl->s, &R, &pl->bb);
-    if (rc) return rc;
-    static_assert(sizeof(Result) == sizeof(mmot_result), "result layout");
-    std::memcpy(res, &R, sizeof R);
-    if (R.status == MMOT_ERR_NUMERIC) return fail(MMOT_ERR_NUMERIC, "non-finite potentials, residual or objective");
-    if (R.status == MMOT_NOT_CONVERGED) {
-        g_err = "itr_max reached before tol";
-        return MMOT_NOT_CONVERGED;
+    try {
+        if (!pl || !log_u || !log_phi || !res) return fail(MMOT_ERR_INVALID, "NULL argument");
+        const int warm = (pl->o.flags & MMOT_FLAG_WARM_START) ? F_WARM : 0;
+        RunOpts o = {pl->o.tol, pl->o.itr_max, pl->o.check_every, plan_path(pl) | F_VALIDATE};
+        Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, warm, 0};
+        Result R;
+        int rc = batch_launch(&pl->hI, &P, 1, pl->p.precision, o, pl->s, &R, &pl->bb);
+        if (rc) return rc;
+        static_assert(sizeof(Result) == sizeof(mmot_result), "result layout");
+        std::memcpy(res, &R, sizeof R);
+        if (R.status == MMOT_ERR_NUMERIC) return fail(MMOT_ERR_NUMERIC, "non-finite potentials, residual or objective");
+        if (R.status == MMOT_NOT_CONVERGED) {
+            g_err = "itr_max reached before tol";
+            return MMOT_NOT_CONVERGED;
+        }
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
     }
-    return MMOT_OK;
 }
 
 int mmot_objective(const mmot_plan_t *pl, const double *log_phi, double *W)
 {
-    if (!pl || !log_phi || !W) return fail(MMOT_ERR_INVALID, "NULL argument");
-    if (pl->tiled) {
-        int rc = plan_tile_pass(pl, P_OBJECTIVE, pl->p.l - 1, nullptr, log_phi, nullptr);
-        if (!rc) rc = plan_tile_sums(pl, pl->p.l - 1, pl->p.l, W);
-        if (rc) return rc;
+    try {
+        if (!pl || !log_phi || !W) return fail(MMOT_ERR_INVALID, "NULL argument");
+        if (pl->tiled) {
+            int rc = plan_tile_pass(pl, P_OBJECTIVE, pl->p.l - 1, nullptr, log_phi, nullptr);
+            if (!rc) rc = plan_tile_sums(pl, pl->p.l - 1, pl->p.l, W);
+            if (rc) return rc;
+            return std::isfinite(*W) ? MMOT_OK : fail(MMOT_ERR_NUMERIC, "non-finite objective");
+        }
+        Ptrs P = {nullptr, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
+        HIPCHK(launch_pass(pl->p.l, MMOT_FP64, 3, pl->dI, P, pl->p.l - 1, pl->dtmp, pl->s));
+        HIPCHK(hipMemcpyAsync(W, pl->dtmp, sizeof(double), hipMemcpyDeviceToHost, pl->s));
+        HIPCHK(hipStreamSynchronize(pl->s));
         return std::isfinite(*W) ? MMOT_OK : fail(MMOT_ERR_NUMERIC, "non-finite objective");
+    } catch (...) {
+        return guard_fail();
     }
-    Ptrs P = {nullptr, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
-    HIPCHK(launch_pass(pl->p.l, MMOT_FP64, 3, pl->dI, P, pl->p.l - 1, pl->dtmp, pl->s));
-    HIPCHK(hipMemcpyAsync(W, pl->dtmp, sizeof(double), hipMemcpyDeviceToHost, pl->s));
-    HIPCHK(hipStreamSynchronize(pl->s));
-    return std::isfinite(*W) ? MMOT_OK : fail(MMOT_ERR_NUMERIC, "non-finite objective");
 }
 
 }  // extern "C"
@@ -372,6 +417,7 @@ hipError_t batch_buffers_alloc(BatchBuffers *bb, size_t c)
     if (e == hipSuccess) e = hipMalloc((void **)&bb->dT, sizeof(Track) * c);
     if (e == hipSuccess) e = hipMalloc((void **)&bb->dTI, sizeof(TileInst) * c);
     if (e == hipSuccess) e = hipMalloc((void **)&bb->dTT, sizeof(TileTrack) * c);
+    if (e == hipSuccess) e = hipMalloc((void **)&bb->dflags, sizeof(int) * c);
     return e;
 }
 
@@ -386,6 +432,7 @@ void batch_buffers_free(BatchBuffers *bb)
     if (bb->dTI) (void)hipFree(bb->dTI);
     if (bb->dTT) (void)hipFree(bb->dTT);
     if (bb->djobs) (void)hipFree(bb->djobs);
+    if (bb->dflags) (void)hipFree(bb->dflags);
     *bb = {};
 }
 
@@ -462,6 +509,18 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     HIPCHK(hipMemcpyAsync(bb->dI, hI, sizeof(Inst) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(bb->dP, hP, sizeof(Ptrs) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(bb->dorder, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    if (flags & F_VALIDATE) {
+        // the marginals must be probability vectors (checked on the device, before any sweep)
+        std::vector<int> bad(count);
+        HIPCHK(launch_check_marginals(bb->dI, bb->dP, count, bb->dflags, s));
+        HIPCHK(hipMemcpyAsync(bad.data(), bb->dflags, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < count; ++i) {
+            if (bad[i] & 1) return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": a marginal entry is NaN or negative");
+            if (bad[i] & 2)
+                return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": a marginal's mass differs from 1 by more than 1e-12");
+        }
+    }
     size_t nother = robust[0].size() + robust[1].size();
     for (int l = 2; l <= MAXL; ++l) nother += wide[l][0].size() + wide[l][1].size() + tiled[l][0].size() + tiled[l][1].size();
     const bool any_fast = nother < (size_t)count;
@@ -670,62 +729,75 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
 
 extern "C" int mmot_last_batch_kernel_ms(double *ms)
 {
-    if (!ms) return fail(MMOT_ERR_INVALID, "NULL argument");
-    std::lock_guard<std::mutex> lk(g_time_mu);
-    if (g_last_kernel_ms < 0) return fail(MMOT_ERR_STATE, "no batch launch yet");
-    *ms = g_last_kernel_ms;
-    return MMOT_OK;
+    try {
+        if (!ms) return fail(MMOT_ERR_INVALID, "NULL argument");
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        if (g_last_kernel_ms < 0) return fail(MMOT_ERR_STATE, "no batch launch yet");
+        *ms = g_last_kernel_ms;
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
+    }
 }
 
 extern "C" int mmot_last_batch_timing(mmot_batch_timing *t)
 {
-    if (!t) return fail(MMOT_ERR_INVALID, "NULL argument");
-    std::lock_guard<std::mutex> lk(g_time_mu);
-    if (g_last_kernel_ms < 0) return fail(MMOT_ERR_STATE, "no batch launch yet");
-    *t = g_last_timing;
-    return MMOT_OK;
+    try {
+        if (!t) return fail(MMOT_ERR_INVALID, "NULL argument");
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        if (g_last_kernel_ms < 0) return fail(MMOT_ERR_STATE, "no batch launch yet");
+        *t = g_last_timing;
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
+    }
 }
 
 extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_t precision, const mmot_opts *o,
                                 void *hip_stream, mmot_result *res)
 {
-    if (count < 0 || (count > 0 && (!inst || !res))) return fail(MMOT_ERR_INVALID, "bad instance list");
-    if (precision != MMOT_FP64 && precision != MMOT_FP32) return fail(MMOT_ERR_INVALID, "bad precision");
-    int rc = check_opts(o);
-    if (rc) return rc;
-    if (count == 0) return MMOT_OK;
-    std::vector<Inst> hI(count);
-    std::vector<Ptrs> hP(count);
-    size_t off = 0;
-    std::vector<size_t> offs(count);
-    for (int i = 0; i < count; ++i) {
-        rc = check_shape(inst[i].l, inst[i].N, inst[i].h, inst[i].eps);
-        if (rc) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
-        if (!inst[i].log_u || !inst[i].log_phi) return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": NULL buffer");
-        hI[i] = make_inst(inst[i].l, inst[i].N, inst[i].h, inst[i].eps);
-        offs[i] = off;
-        off += scratch_bytes(inst[i].l, inst[i].N, precision, (o->flags & MMOT_FLAG_TILES) ? F_TILES : 0);
+    try {
+        if (count < 0 || (count > 0 && (!inst || !res))) return fail(MMOT_ERR_INVALID, "bad instance list");
+        if (precision != MMOT_FP64 && precision != MMOT_FP32) return fail(MMOT_ERR_INVALID, "bad precision");
+        int rc = check_opts(o);
+        if (rc) return rc;
+        if (count == 0) return MMOT_OK;
+        std::vector<Inst> hI(count);
+        std::vector<Ptrs> hP(count);
+        size_t off = 0;
+        std::vector<size_t> offs(count);
+        for (int i = 0; i < count; ++i) {
+            rc = check_shape(inst[i].l, inst[i].N, inst[i].h, inst[i].eps);
+            if (rc) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+            if (!inst[i].log_u || !inst[i].log_phi) return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": NULL buffer");
+            hI[i] = make_inst(inst[i].l, inst[i].N, inst[i].h, inst[i].eps);
+            offs[i] = off;
+            off += scratch_bytes(inst[i].l, inst[i].N, precision, (o->flags & MMOT_FLAG_TILES) ? F_TILES : 0);
+        }
+        std::lock_guard<std::mutex> lk(g_batch.mu);
+        rc = g_batch.reserve((size_t)count, std::max<size_t>(off, 256));
+        if (rc) return rc;
+        for (int i = 0; i < count; ++i)
+            hP[i] = {inst[i].log_u, inst[i].log_phi, nullptr, g_batch.scratch + offs[i], 0, 0,
+                     (o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0, 0};
+        RunOpts ro = {o->tol, o->itr_max, o->check_every,
+                      ((o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | ((o->flags & MMOT_FLAG_TILES) ? F_TILES : 0) |
+                          F_VALIDATE, 0,
+                      FAST_WARMUP_SWEEPS};
+        BatchBuffers bb = g_batch.bb;
+        std::vector<Result> hR(count);
+        rc = batch_launch(hI.data(), hP.data(), count, precision, ro, (hipStream_t)hip_stream, hR.data(), &bb, true);
+        if (rc) return rc;
+        int worst = MMOT_OK;
+        for (int i = 0; i < count; ++i) {
+            std::memcpy(&res[i], &hR[i], sizeof(Result));
+            if (hR[i].status == MMOT_ERR_NUMERIC) worst = MMOT_ERR_NUMERIC;
+            else if (hR[i].status == MMOT_NOT_CONVERGED && worst == MMOT_OK) worst = MMOT_NOT_CONVERGED;
+        }
+        if (worst == MMOT_ERR_NUMERIC) return fail(MMOT_ERR_NUMERIC, "some instances produced non-finite values");
+        if (worst == MMOT_NOT_CONVERGED) g_err = "some instances reached itr_max";
+        return worst;
+    } catch (...) {
+        return guard_fail();
     }
-    std::lock_guard<std::mutex> lk(g_batch.mu);
-    rc = g_batch.reserve((size_t)count, std::max<size_t>(off, 256));
-    if (rc) return rc;
-    for (int i = 0; i < count; ++i)
-        hP[i] = {inst[i].log_u, inst[i].log_phi, nullptr, g_batch.scratch + offs[i], 0, 0,
-                 (o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0, 0};
-    RunOpts ro = {o->tol, o->itr_max, o->check_every,
-                  ((o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | ((o->flags & MMOT_FLAG_TILES) ? F_TILES : 0), 0,
-                  FAST_WARMUP_SWEEPS};
-    BatchBuffers bb = g_batch.bb;
-    std::vector<Result> hR(count);
-    rc = batch_launch(hI.data(), hP.data(), count, precision, ro, (hipStream_t)hip_stream, hR.data(), &bb, true);
-    if (rc) return rc;
-    int worst = MMOT_OK;
-    for (int i = 0; i < count; ++i) {
-        std::memcpy(&res[i], &hR[i], sizeof(Result));
-        if (hR[i].status == MMOT_ERR_NUMERIC) worst = MMOT_ERR_NUMERIC;
-        else if (hR[i].status == MMOT_NOT_CONVERGED && worst == MMOT_OK) worst = MMOT_NOT_CONVERGED;
-    }
-    if (worst == MMOT_ERR_NUMERIC) return fail(MMOT_ERR_NUMERIC, "some instances produced non-finite values");
-    if (worst == MMOT_NOT_CONVERGED) g_err = "some instances reached itr_max";
-    return worst;
 }

@@ -8,6 +8,55 @@ namespace mmot {
 
 __global__ void k_fill_int(int *p, int v) { *p = v; }
 
+__global__ void k_zero_int(int *p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// One block per (instance, row): compensated per-thread sums of exp(log u),
+// then a tree over the block.
+__global__ __launch_bounds__(256) void k_check_marginals(const Inst *I, const Ptrs *P, int count, int *flags)
+{
+    const int i = blockIdx.x, q = blockIdx.y;
+    if (i >= count || q >= I[i].l) return;
+    const long N = I[i].N;
+    const double *lu = P[i].log_u + (long)q * N;
+    __shared__ double red[256];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    double s = 0.0, c = 0.0;
+    int b = 0;
+    for (long p = threadIdx.x; p < N; p += blockDim.x) {
+        const double x = lu[p];
+        if (x != x || x == INFINITY) b = 1;
+        const double y = exp(x) - c;
+        const double t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    if (b) atomicOr(&bad, 1);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int f = bad;
+        if (!(fabs(red[0] - 1.0) <= 1e-12)) f |= 2;
+        if (f) atomicOr(&flags[i], f);
+    }
+}
+
+hipError_t launch_check_marginals(const Inst *dI, const Ptrs *dP, int count, int *dflags, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_int, dim3(std::min((count + 255) / 256, 1024)), dim3(256), 0, s, dflags, count);
+    hipLaunchKernelGGL(k_check_marginals, dim3(count, MAXL), dim3(256), 0, s, dI, dP, count, dflags);
+    return hipGetLastError();
+}
+
 // phi = 1/N (Alg. 1 initialisation) for the listed instances that do not start warm.
 __global__ void k_tile_init(const Inst *I, const Ptrs *P, const int *list, int count, RunOpts o)
 {

@@ -69,6 +69,11 @@ hipError_t launch_tile_pass(int l, int precision, int mode, const Inst *dI, cons
 // which 0: estimate and check decision after a sweep; 1: residual and stop decision after a check.
 hipError_t launch_tile_ctrl(int l, int which, const Ptrs *dP, const TileInst *dTI, TileTrack *dTr, int count,
                             const RunOpts &o, hipStream_t s);
+// Marginal checks of `count` instances: flags[i] |= 1 if a log u entry of
+// instance i is NaN or +inf, |= 2 if a row's mass differs from 1 by more than
+// 1e-12 (FP64).  flags must be zero on entry.
+hipError_t launch_check_marginals(const Inst *dI, const Ptrs *dP, int count, int *dflags, hipStream_t s);
+
 // phi = 1/N for the listed instances that do not start warm.
 hipError_t launch_tile_init(const Inst *dI, const Ptrs *dP, const int *dlist, int count, const RunOpts &o,
                             hipStream_t s);

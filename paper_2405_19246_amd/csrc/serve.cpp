@@ -279,171 +279,195 @@ extern "C" {
 
 int mmot_serve_start(const mmot_serve_cfg *cfg, mmot_server_t **out)
 {
-    if (!cfg || !out) return fail(MMOT_ERR_INVALID, "NULL argument");
-    *out = nullptr;
-    if (cfg->precision != MMOT_FP64 && cfg->precision != MMOT_FP32) return fail(MMOT_ERR_INVALID, "bad precision");
-    int rc = check_opts(&cfg->opts);
-    if (rc) return rc;
-    if (cfg->max_slots < 1) return fail(MMOT_ERR_INVALID, "max_slots must be >= 1");
-    if (cfg->block_sweeps < 1) return fail(MMOT_ERR_INVALID, "block_sweeps must be >= 1");
-    if (cfg->hbm_budget_bytes < 4096) return fail(MMOT_ERR_INVALID, "hbm_budget_bytes too small");
-    std::unique_ptr<mmot_server> srv(new mmot_server());
-    srv->cfg = *cfg;
-    if (srv->cfg.opts.itr_max < 1) srv->cfg.opts.itr_max = 1;
-    hipError_t e = hipStreamCreate(&srv->s);
-    if (e == hipSuccess) e = hipMalloc((void **)&srv->base, cfg->hbm_budget_bytes);
-    const size_t c = (size_t)cfg->max_slots;
-    if (e == hipSuccess) e = batch_buffers_alloc(&srv->bb, c);
-    if (e != hipSuccess) {
-        mmot_server *p = srv.release();
-        if (p->base) (void)hipFree(p->base);
-        batch_buffers_free(&p->bb);
-        if (p->s) (void)hipStreamDestroy(p->s);
-        delete p;
-        return fail(e == hipErrorOutOfMemory ? MMOT_ERR_NOMEM : MMOT_ERR_HIP,
-                    std::string("server allocation: ") + hipGetErrorString(e));
+    try {
+        if (!cfg || !out) return fail(MMOT_ERR_INVALID, "NULL argument");
+        *out = nullptr;
+        if (cfg->precision != MMOT_FP64 && cfg->precision != MMOT_FP32) return fail(MMOT_ERR_INVALID, "bad precision");
+        int rc = check_opts(&cfg->opts);
+        if (rc) return rc;
+        if (cfg->max_slots < 1) return fail(MMOT_ERR_INVALID, "max_slots must be >= 1");
+        if (cfg->block_sweeps < 1) return fail(MMOT_ERR_INVALID, "block_sweeps must be >= 1");
+        if (cfg->hbm_budget_bytes < 4096) return fail(MMOT_ERR_INVALID, "hbm_budget_bytes too small");
+        std::unique_ptr<mmot_server> srv(new mmot_server());
+        srv->cfg = *cfg;
+        if (srv->cfg.opts.itr_max < 1) srv->cfg.opts.itr_max = 1;
+        hipError_t e = hipStreamCreate(&srv->s);
+        if (e == hipSuccess) e = hipMalloc((void **)&srv->base, cfg->hbm_budget_bytes);
+        const size_t c = (size_t)cfg->max_slots;
+        if (e == hipSuccess) e = batch_buffers_alloc(&srv->bb, c);
+        if (e != hipSuccess) {
+            mmot_server *p = srv.release();
+            if (p->base) (void)hipFree(p->base);
+            batch_buffers_free(&p->bb);
+            if (p->s) (void)hipStreamDestroy(p->s);
+            delete p;
+            return fail(e == hipErrorOutOfMemory ? MMOT_ERR_NOMEM : MMOT_ERR_HIP,
+                        std::string("server allocation: ") + hipGetErrorString(e));
+        }
+        srv->arena.init(cfg->hbm_budget_bytes);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        mmot_server *raw = srv.get();
+        raw->th = std::thread([raw, dev] {
+            (void)hipSetDevice(dev);
+            raw->loop();
+        });
+        *out = srv.release();
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
     }
-    srv->arena.init(cfg->hbm_budget_bytes);
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    mmot_server *raw = srv.get();
-    raw->th = std::thread([raw, dev] {
-        (void)hipSetDevice(dev);
-        raw->loop();
-    });
-    *out = srv.release();
-    return MMOT_OK;
 }
 
 int mmot_serve_submit(mmot_server_t *srv, const mmot_request *req, uint64_t *ticket)
 {
-    if (!srv || !req || !ticket || !req->u) return fail(MMOT_ERR_INVALID, "NULL argument");
-    int rc = check_shape(req->l, req->N, req->h, req->eps);
-    if (rc) return rc;
-    const size_t n = (size_t)req->l * (size_t)req->N;
-    std::unique_ptr<Request> r(new Request());
-    r->l = req->l;
-    r->N = req->N;
-    r->h = req->h;
-    r->eps = req->eps;
-    r->log_u.resize(n);
-    for (int q = 0; q < req->l; ++q) {
-        double mass = 0.0;
-        for (int64_t i = 0; i < req->N; ++i) {
-            const double v = req->u[(size_t)q * req->N + i];
-            if (!(v >= 0.0) || !std::isfinite(v)) return fail(MMOT_ERR_INVALID, "marginal entries must be finite and >= 0");
-            mass += v;
-            r->log_u[(size_t)q * req->N + i] = std::log(v);
+    try {
+        if (!srv || !req || !ticket || !req->u) return fail(MMOT_ERR_INVALID, "NULL argument");
+        int rc = check_shape(req->l, req->N, req->h, req->eps);
+        if (rc) return rc;
+        const size_t n = (size_t)req->l * (size_t)req->N;
+        std::unique_ptr<Request> r(new Request());
+        r->l = req->l;
+        r->N = req->N;
+        r->h = req->h;
+        r->eps = req->eps;
+        r->log_u.resize(n);
+        for (int q = 0; q < req->l; ++q) {
+            double mass = 0.0, comp = 0.0;  // compensated sum: long rows stay well inside 1e-12
+            for (int64_t i = 0; i < req->N; ++i) {
+                const double v = req->u[(size_t)q * req->N + i];
+                if (!(v >= 0.0) || !std::isfinite(v)) return fail(MMOT_ERR_INVALID, "marginal entries must be finite and >= 0");
+                const double y = v - comp, t = mass + y;
+                comp = (t - mass) - y;
+                mass = t;
+                r->log_u[(size_t)q * req->N + i] = std::log(v);
+            }
+            if (!(std::fabs(mass - 1.0) <= 1e-12)) return fail(MMOT_ERR_INVALID, "each marginal must sum to 1");
         }
-        if (!(std::fabs(mass - 1.0) <= 1e-9)) return fail(MMOT_ERR_INVALID, "each marginal must sum to 1");
+        if (request_bytes(req->l, req->N, srv->cfg.precision, srv->tile_flag()) > srv->cfg.hbm_budget_bytes)
+            return fail(MMOT_ERR_NOMEM, "request footprint exceeds the server's HBM budget");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stopping) return fail(MMOT_ERR_STATE, "server is stopping");
+        r->ticket = srv->next_ticket++;
+        r->t_submit = now_s();
+        *ticket = r->ticket;
+        srv->queue.push_back(std::move(r));
+        srv->cv.notify_all();
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
     }
-    if (request_bytes(req->l, req->N, srv->cfg.precision, srv->tile_flag()) > srv->cfg.hbm_budget_bytes)
-        return fail(MMOT_ERR_NOMEM, "request footprint exceeds the server's HBM budget");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->stopping) return fail(MMOT_ERR_STATE, "server is stopping");
-    r->ticket = srv->next_ticket++;
-    r->t_submit = now_s();
-    *ticket = r->ticket;
-    srv->queue.push_back(std::move(r));
-    srv->cv.notify_all();
-    return MMOT_OK;
 }
 
 int mmot_serve_poll(mmot_server_t *srv, uint64_t ticket, mmot_request_record *rec, double *log_phi_out)
 {
-    if (!srv || !rec) return fail(MMOT_ERR_INVALID, "NULL argument");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->error) return fail(srv->error, srv->error_msg);
-    auto it = srv->done.find(ticket);
-    if (it == srv->done.end()) {
-        if (ticket == 0 || ticket >= srv->next_ticket) return fail(MMOT_ERR_STATE, "unknown ticket");
-        return 0;
+    try {
+        if (!srv || !rec) return fail(MMOT_ERR_INVALID, "NULL argument");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->error) return fail(srv->error, srv->error_msg);
+        auto it = srv->done.find(ticket);
+        if (it == srv->done.end()) {
+            if (ticket == 0 || ticket >= srv->next_ticket) return fail(MMOT_ERR_STATE, "unknown ticket");
+            return 0;
+        }
+        *rec = it->second.rec;
+        if (log_phi_out) std::memcpy(log_phi_out, it->second.log_phi.data(), sizeof(double) * it->second.log_phi.size());
+        return 1;
+    } catch (...) {
+        return guard_fail();
     }
-    *rec = it->second.rec;
-    if (log_phi_out) std::memcpy(log_phi_out, it->second.log_phi.data(), sizeof(double) * it->second.log_phi.size());
-    return 1;
 }
 
 int mmot_serve_stop(mmot_server_t *srv)
 {
-    if (!srv) return MMOT_OK;
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        srv->stopping = true;
+    try {
+        if (!srv) return MMOT_OK;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->stopping = true;
+        }
+        srv->cv.notify_all();
+        if (srv->th.joinable()) srv->th.join();
+        const int err = srv->error;
+        const std::string msg = srv->error_msg;
+        (void)hipFree(srv->base);
+        batch_buffers_free(&srv->bb);
+        (void)hipStreamDestroy(srv->s);
+        delete srv;
+        return err ? fail(err, msg) : MMOT_OK;
+    } catch (...) {
+        return guard_fail();
     }
-    srv->cv.notify_all();
-    if (srv->th.joinable()) srv->th.join();
-    const int err = srv->error;
-    const std::string msg = srv->error_msg;
-    (void)hipFree(srv->base);
-    batch_buffers_free(&srv->bb);
-    (void)hipStreamDestroy(srv->s);
-    delete srv;
-    return err ? fail(err, msg) : MMOT_OK;
 }
 
 int mmot_serve(const mmot_serve_cfg *cfg, mmot_request_fn next, void *user, mmot_serve_stats *stats,
                mmot_request_record *records, int64_t max_records)
 {
-    if (!cfg || !next || !stats) return fail(MMOT_ERR_INVALID, "NULL argument");
-    mmot_server_t *srv = nullptr;
-    int rc = mmot_serve_start(cfg, &srv);
-    if (rc) return rc;
-    std::vector<uint64_t> tickets;
-    int64_t rejected = 0;
-    const double t0 = now_s();
-    for (int64_t idx = 0;; ++idx) {
-        mmot_request req;
-        double t_arr = 0.0;
-        if (next(user, idx, &req, &t_arr) != 0) break;
-        const double wait = t0 + t_arr - now_s();
-        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
-        uint64_t tk = 0;
-        rc = mmot_serve_submit(srv, &req, &tk);
-        if (rc == MMOT_ERR_NOMEM) {
-            ++rejected;
-            continue;
-        }
-        if (rc) {
-            mmot_serve_stop(srv);
-            return rc;
-        }
-        tickets.push_back(tk);
-    }
-    std::vector<double> lat;
-    double units = 0.0, t_last = t0;
-    int64_t k = 0;
-    for (uint64_t tk : tickets) {
-        mmot_request_record rec;
-        for (;;) {
-            rc = mmot_serve_poll(srv, tk, &rec, nullptr);
-            if (rc == 1) break;
-            if (rc < 0) {
+    try {
+        if (!cfg || !next || !stats) return fail(MMOT_ERR_INVALID, "NULL argument");
+        mmot_server_t *srv = nullptr;
+        int rc = mmot_serve_start(cfg, &srv);
+        if (rc) return rc;
+        std::vector<uint64_t> tickets;
+        int64_t rejected = 0;
+        const double t0 = now_s();
+        for (int64_t idx = 0;; ++idx) {
+            mmot_request req;
+            double t_arr = 0.0;
+            if (next(user, idx, &req, &t_arr) != 0) break;
+            const double wait = t0 + t_arr - now_s();
+            if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+            uint64_t tk = 0;
+            rc = mmot_serve_submit(srv, &req, &tk);
+            if (rc == MMOT_ERR_NOMEM || rc == MMOT_ERR_INVALID || rc == MMOT_ERR_UNSUPPORTED) {
+                // footprint above the whole budget, or a request the library does not take:
+                // counted as rejected, the others are served
+                ++rejected;
+                continue;
+            }
+            if (rc) {
                 mmot_serve_stop(srv);
                 return rc;
             }
-            std::this_thread::sleep_for(std::chrono::microseconds(200));
+            tickets.push_back(tk);
         }
-        lat.push_back(rec.t_done - rec.t_submit);
-        units += (double)rec.result.l * (double)rec.result.N * (double)rec.result.iters;
-        t_last = std::max(t_last, rec.t_done);
-        if (records && k < max_records) records[k] = rec;
-        ++k;
+        std::vector<double> lat;
+        double units = 0.0, t_last = t0;
+        int64_t k = 0;
+        for (uint64_t tk : tickets) {
+            mmot_request_record rec;
+            for (;;) {
+                rc = mmot_serve_poll(srv, tk, &rec, nullptr);
+                if (rc == 1) break;
+                if (rc < 0) {
+                    mmot_serve_stop(srv);
+                    return rc;
+                }
+                std::this_thread::sleep_for(std::chrono::microseconds(200));
+            }
+            lat.push_back(rec.t_done - rec.t_submit);
+            units += (double)rec.result.l * (double)rec.result.N * (double)rec.result.iters;
+            t_last = std::max(t_last, rec.t_done);
+            if (records && k < max_records) records[k] = rec;
+            ++k;
+        }
+        rc = mmot_serve_stop(srv);
+        std::sort(lat.begin(), lat.end());
+        auto pct = [&](double q) {
+            if (lat.empty()) return 0.0;
+            const size_t i = std::min(lat.size() - 1, (size_t)std::ceil(q * (double)lat.size()) - (q > 0 ? 1 : 0));
+            return lat[i];
+        };
+        stats->completed = (int64_t)lat.size();
+        stats->rejected = rejected;
+        stats->wall_seconds = t_last - t0;
+        stats->p50_latency = pct(0.50);
+        stats->p99_latency = pct(0.99);
+        stats->units_per_second = stats->wall_seconds > 0 ? units / stats->wall_seconds : 0.0;
+        return rc;
+    } catch (...) {
+        return guard_fail();
     }
-    rc = mmot_serve_stop(srv);
-    std::sort(lat.begin(), lat.end());
-    auto pct = [&](double q) {
-        if (lat.empty()) return 0.0;
-        const size_t i = std::min(lat.size() - 1, (size_t)std::ceil(q * (double)lat.size()) - (q > 0 ? 1 : 0));
-        return lat[i];
-    };
-    stats->completed = (int64_t)lat.size();
-    stats->rejected = rejected;
-    stats->wall_seconds = t_last - t0;
-    stats->p50_latency = pct(0.50);
-    stats->p99_latency = pct(0.99);
-    stats->units_per_second = stats->wall_seconds > 0 ? units / stats->wall_seconds : 0.0;
-    return rc;
 }
 
 }  // extern "C"

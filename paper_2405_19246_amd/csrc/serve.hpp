@@ -25,6 +25,7 @@ struct BatchBuffers {
     TileTrack *dTT;   // tiled solves: per-instance state
     char *djobs;      // tiled solves: job lists (grow-only)
     size_t jobs_cap;
+    int *dflags;      // marginal checks: per-instance flags
 };
 
 // Job lists of the tiled launches of instances g (all with l marginals) in bb's
@@ -48,6 +49,8 @@ void batch_buffers_free(BatchBuffers *bb);
 namespace rt {
 extern thread_local std::string g_err;
 int fail(int code, const std::string &msg);
+// Maps the exception being handled to an MMOT_* code (inside a catch block).
+int guard_fail();
 int check_shape(int l, int64_t N, double h, double eps);
 int check_opts(const mmot_opts *o);
 }  // namespace rt
