@@ -173,7 +173,13 @@ constexpr int elem_bytes(int kind) { return kind == 0 ? 8 : kind == 2 ? 32 : 16;
 constexpr int WIDE_MINL = 7;   // l from which batches and plans use the team layout
 constexpr int WIDE_MAXL = 10;  // largest l the team layout is built for
 constexpr int wide_states(int l) { return 1 << (l - 1); }
-constexpr int wide_tl(int l) { return wide_states(l) < WAVE ? wide_states(l) : WAVE; }
+// lanes per team: the states of l <= 4 one per lane; beyond, 16 lanes (the
+// lane moves stay inside DPP rows) with up to 8 states per lane, growing to 32
+// and 64 lanes for l = 9, 10 so that the FP64 states of a lane stay near 8
+constexpr int wide_tl(int l)
+{
+    return l <= 4 ? wide_states(l) : (wide_states(l) / 8 > 16 ? wide_states(l) / 8 : 16);
+}
 constexpr int wide_rg(int l) { return wide_states(l) / wide_tl(l); }
 // positions per recompute block: about 48 registers of forward states per lane
 constexpr int wide_ck(int l, int words)

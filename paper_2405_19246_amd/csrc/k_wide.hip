@@ -11,6 +11,8 @@
 
 namespace mmot {
 
+static __global__ void k_fill_int1(int *p, int v) { *p = v; }
+
 template <int L>
 static hipError_t wide_pass_t(int precision, int mode, const Inst *dI, const Ptrs &P, int j, double *dres,
                               hipStream_t s)
@@ -47,6 +49,9 @@ static hipError_t wide_batch_t(int precision, const Inst *dI, const Ptrs *dP, co
     else
         hipLaunchKernelGGL((k_wide_batch<L, double>), dim3(blocks), dim3(WAVE), 0, s, dI, dP, dorder, count, o, dR,
                            dticket);
+    // the objective of the solves that ended cleanly, in a launch of its own
+    hipLaunchKernelGGL(k_fill_int1, dim3(1), dim3(1), 0, s, dticket, 0);
+    hipLaunchKernelGGL((k_wide_objective<L>), dim3(blocks), dim3(WAVE), 0, s, dI, dP, dorder, count, o, dR, dticket);
     return hipGetLastError();
 }
 

@@ -415,8 +415,10 @@ __device__ __forceinline__ WTeam<L, E> make_team(char *lds, void *scratch)
     return tm;
 }
 
-// Whole solve of one instance on one team (Alg. 1 loop: Gauss-Seidel updates in
-// precision M, FP64 residual, FP64 objective), same stopping rule as solve_one.
+// Sweeps of one instance on one team (Alg. 1 loop: Gauss-Seidel updates in
+// precision M, FP64 residual), same stopping rule as solve_one.  The objective
+// follows in its own launch (k_wide_objective), so that its wider elements do
+// not set this kernel's register count.
 template <int L, typename M>
 __device__ void wide_solve(char *lds, const Inst *__restrict__ I, const Ptrs P, const RunOpts o,
                            Result *__restrict__ R)
@@ -424,7 +426,6 @@ __device__ void wide_solve(char *lds, const Inst *__restrict__ I, const Ptrs P, 
     using EU = XF<M>;
     const WTeam<L, EU> tu = make_team<L, EU>(lds, P.scratch);
     const WTeam<L, XF<double>> tc = make_team<L, XF<double>>(lds, P.scratch);
-    const WTeam<L, DXF> to = make_team<L, DXF>(lds, P.scratch);
     constexpr int TL = WL<L, EU>::TL;
     const long N = I->N;
     double *a = P.a;
@@ -471,15 +472,9 @@ __device__ void wide_solve(char *lds, const Inst *__restrict__ I, const Ptrs P, 
             if (trig) f *= 0.5;
         }
     }
-    double W = 0.0;
-    if (status == ST_OK && !(flags & F_NO_OBJ)) {
-        const WAcc w = wide_pass<L, DXF, P_OBJECTIVE>(to, I, L - 1, a, lu, nullptr, 0, N, nullptr, nullptr);
-        W = I->h * xto_double(w.x);
-        if (!(W == W) || W == INFINITY) status = ST_NUMERIC;
-    }
     if (status == ST_OK && checked && o.tol >= 0.0 && !(res <= o.tol)) status = ST_NOT_CONVERGED;
     if (tu.last) {
-        R->W = W;
+        R->W = 0.0;
         R->marg_err = res;
         R->iters = it;
         R->status = status;
@@ -501,6 +496,31 @@ __global__ __launch_bounds__(64) void k_wide_batch(const Inst *I, const Ptrs *P,
         if (tk >= count) break;
         const int idx = order[tk];
         wide_solve<L, M>(lds, &I[idx], P[idx], o, &R[idx]);
+    }
+}
+
+// FP64 objective (Sec. 2 Eq. mmot distance) of the listed instances whose solve
+// ended with status ST_OK (unless F_NO_OBJ), one team each; a non-finite value
+// turns the status into ST_NUMERIC.
+template <int L>
+__global__ __launch_bounds__(64) void k_wide_objective(const Inst *I, const Ptrs *P, const int *order, int count,
+                                                       RunOpts o, Result *R, int *ticket)
+{
+    __shared__ __attribute__((aligned(16))) char lds[WShared<L>::TPWMAX * WShared<L>::BYTES];
+    const int t = (int)threadIdx.x & (WL<L, DXF>::TL - 1);
+    for (;;) {
+        const int tk = team_ticket<L, DXF>(ticket, t);
+        if (tk >= count) break;
+        const int idx = order[tk];
+        if (R[idx].status != ST_OK || ((o.flags | P[idx].flags) & F_NO_OBJ)) continue;
+        const WTeam<L, DXF> to = make_team<L, DXF>(lds, P[idx].scratch);
+        const WAcc w = wide_pass<L, DXF, P_OBJECTIVE>(to, &I[idx], L - 1, P[idx].a, P[idx].log_u, nullptr, 0,
+                                                      I[idx].N, nullptr, nullptr);
+        if (to.last) {
+            const double W = I[idx].h * xto_double(w.x);
+            R[idx].W = W;
+            if (!(W == W) || W == INFINITY) R[idx].status = ST_NUMERIC;
+        }
     }
 }
 
