@@ -271,6 +271,13 @@ int mmot_serve_poll(mmot_server_t *srv, uint64_t ticket, mmot_request_record *re
 /* Finish queued and running work, stop the thread, free the device arena. */
 int mmot_serve_stop(mmot_server_t *srv);
 
+/* Shed the load: requests still queued are finished at once with status
+ * MMOT_ERR_STATE (not started), requests on the device end after the current
+ * device round with their last residual (status MMOT_NOT_CONVERGED unless it
+ * met tol), and no new request is accepted.  Does not wait; mmot_serve_stop
+ * then returns after at most that round. */
+int mmot_serve_cancel(mmot_server_t *srv);
+
 /* Summary of a blocking serving run. */
 typedef struct {
     int64_t completed;

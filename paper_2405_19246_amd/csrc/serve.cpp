@@ -131,6 +131,7 @@ struct mmot_server {
     std::map<uint64_t, Done> done;
     uint64_t next_ticket = 1;
     bool stopping = false;
+    bool cancel = false;  // mmot_serve_cancel: running solves end after the current round
     int error = MMOT_OK;
     std::string error_msg;
 
@@ -258,7 +259,7 @@ void mmot_server::loop()
             sl.started = true;
             sl.iters += hR[i].iters;
             const bool conv = cfg.opts.tol >= 0 && hR[i].marg_err <= cfg.opts.tol;
-            if (conv || hR[i].status == MMOT_ERR_NUMERIC || sl.iters >= cfg.opts.itr_max) fin.push_back(i);
+            if (conv || hR[i].status == MMOT_ERR_NUMERIC || sl.iters >= cfg.opts.itr_max || cancel) fin.push_back(i);
         }
         if (!fin.empty()) {
             rc = finish(slots, fin, hR);
@@ -373,6 +374,34 @@ int mmot_serve_poll(mmot_server_t *srv, uint64_t ticket, mmot_request_record *re
         *rec = it->second.rec;
         if (log_phi_out) std::memcpy(log_phi_out, it->second.log_phi.data(), sizeof(double) * it->second.log_phi.size());
         return 1;
+    } catch (...) {
+        return guard_fail();
+    }
+}
+
+int mmot_serve_cancel(mmot_server_t *srv)
+{
+    try {
+        if (!srv) return fail(MMOT_ERR_INVALID, "NULL argument");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        const double t = now_s();
+        for (auto &r : srv->queue) {
+            Done d;
+            std::memset(&d.rec, 0, sizeof d.rec);
+            d.rec.result.status = MMOT_ERR_STATE;
+            d.rec.result.l = r->l;
+            d.rec.result.N = r->N;
+            d.rec.result.marg_err = INFINITY;
+            d.rec.t_submit = r->t_submit;
+            d.rec.t_admit = t;
+            d.rec.t_done = t;
+            srv->done[r->ticket] = std::move(d);
+        }
+        srv->queue.clear();
+        srv->cancel = true;
+        srv->stopping = true;
+        srv->cv.notify_all();
+        return MMOT_OK;
     } catch (...) {
         return guard_fail();
     }

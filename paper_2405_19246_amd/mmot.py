@@ -73,7 +73,7 @@ REQUEST_FN = ctypes.CFUNCTYPE(ctypes.c_int, _c_p, _c_i64, ctypes.POINTER(Request
 
 EXPORTS = ["mmot_plan", "mmot_plan_footprint", "mmot_plan_destroy", "mmot_marginal_product", "mmot_sinkhorn_iter",
            "mmot_solve", "mmot_objective", "mmot_marginal_errors", "mmot_solve_batch", "mmot_serve_start",
-           "mmot_serve_submit", "mmot_serve_poll", "mmot_serve_stop", "mmot_serve", "mmot_last_batch_kernel_ms",
+           "mmot_serve_submit", "mmot_serve_poll", "mmot_serve_stop", "mmot_serve_cancel", "mmot_serve", "mmot_last_batch_kernel_ms",
            "mmot_last_batch_timing", "mmot_marginal_product_noalloc", "mmot_last_error"]
 
 
@@ -114,6 +114,7 @@ def lib() -> ctypes.CDLL:
         L.mmot_serve_submit.argtypes = [_c_p, PP(Request), PP(ctypes.c_uint64)]
         L.mmot_serve_poll.argtypes = [_c_p, ctypes.c_uint64, PP(RequestRecord), _c_p]
         L.mmot_serve_stop.argtypes = [_c_p]
+        L.mmot_serve_cancel.argtypes = [_c_p]
         L.mmot_serve.argtypes = [PP(ServeCfg), REQUEST_FN, _c_p, PP(ServeStats), PP(RequestRecord), _c_i64]
         L.mmot_last_batch_kernel_ms.argtypes = [PP(_c_d)]
         L.mmot_last_batch_timing.argtypes = [PP(BatchTiming)]
@@ -314,6 +315,11 @@ class Server:
         if buf is not None:
             out["log_phi"] = buf
         return out
+
+    def cancel(self):
+        """mmot_serve_cancel: drop queued requests, end running ones after the current round."""
+        if getattr(self, "_h", None):
+            _check(lib().mmot_serve_cancel(self._h))
 
     def stop(self):
         if getattr(self, "_h", None):
