@@ -80,7 +80,11 @@ typedef struct {
  * flags: MMOT_FLAG_WARM_START keeps the potentials passed in instead of
  * starting from phi = 1/N (Alg. 1 init); MMOT_FLAG_NO_FAST runs every solve on
  * the extended-range solver (one wavefront per solve) instead of the
- * register-resident one (one workgroup per solve, taken when N fits it). */
+ * register-resident one (one workgroup per solve, taken when N fits it);
+ * MMOT_FLAG_TILES cuts every instance into tiles (otherwise only long ones:
+ * N >= 16384 for l <= 6, N >= 4096 for l >= 7); MMOT_FLAG_NO_GRAPH launches
+ * the tiled sweeps one by one instead of replaying a captured HIP graph of a
+ * block of sweeps (same iterates, bit for bit). */
 typedef struct {
     double tol;
     int64_t itr_max;
@@ -91,6 +95,7 @@ typedef struct {
 #define MMOT_FLAG_WARM_START 1
 #define MMOT_FLAG_NO_FAST 2
 #define MMOT_FLAG_TILES 4
+#define MMOT_FLAG_NO_GRAPH 8
 
 /* Per-solve outcome. */
 typedef struct {

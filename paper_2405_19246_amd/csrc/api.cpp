@@ -91,7 +91,10 @@ struct mmot_plan {
     mutable std::vector<char> jobs_host;
 };
 
-static int plan_flags(const mmot_opts &o) { return (o.flags & MMOT_FLAG_TILES) ? F_TILES : 0; }
+static int plan_flags(const mmot_opts &o)
+{
+    return ((o.flags & MMOT_FLAG_TILES) ? F_TILES : 0) | ((o.flags & MMOT_FLAG_NO_GRAPH) ? F_NO_GRAPH : 0);
+}
 
 extern "C" {
 
@@ -782,6 +785,7 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
                      (o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0, 0};
         RunOpts ro = {o->tol, o->itr_max, o->check_every,
                       ((o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | ((o->flags & MMOT_FLAG_TILES) ? F_TILES : 0) |
+                          ((o->flags & MMOT_FLAG_NO_GRAPH) ? F_NO_GRAPH : 0) |
                           F_VALIDATE, 0,
                       FAST_WARMUP_SWEEPS};
         BatchBuffers bb = g_batch.bb;

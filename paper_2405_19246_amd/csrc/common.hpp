@@ -120,6 +120,8 @@ constexpr int32_t F_NO_OBJ = 4;      // skip the objective
 constexpr int32_t F_NO_FAST = 8;     // host only: every instance on the extended-range solver
 constexpr int32_t F_TILES = 16;      // host only: every instance is tiled (tests and small shapes)
 constexpr int32_t F_VALIDATE = 32;   // host only: check the marginals before solving
+constexpr int32_t F_NO_GRAPH = 64;   // host only: tiled sweep blocks launched one by one, not as a graph
+constexpr int TILE_GRAPH_SWEEPS = 8; // sweeps per captured block of a tiled solve
 
 // Lane width V per (l, pass kind) -- trades registers against scan overhead.
 // kind 0: FP32 update, 1: FP64 update and product, 2: FP64 objective

@@ -20,7 +20,8 @@ static hipError_t tile_pass_t(const Inst *dI, const Ptrs *dP, const TileInst *dT
         hipLaunchKernelGGL((k_tile_agg<L, E>), dim3((J.n1 + tpw - 1) / tpw), dim3(WAVE), 0, s, dI, dP, dTI, dTr,
                            J.agg, J.n1, j, state_need);
     if (J.n2 > 0)
-        hipLaunchKernelGGL((k_tile_chain<L, E>), dim3(J.n2), dim3(256), 0, s, dTI, dTr, J.chain, J.n2, state_need);
+        hipLaunchKernelGGL((k_tile_chain<L, E>), dim3(J.n2), dim3(CHAIN_THREADS), 0, s, dTI, dTr, J.chain, J.n2,
+                           state_need);
     if (J.n3 > 0)
         hipLaunchKernelGGL((k_tile_final<L, E, MODE>), dim3((J.n3 + tpw - 1) / tpw), dim3(WAVE), 0, s, dI, dP, dTI,
                            dTr, J.fin, J.n3, j, state_need);

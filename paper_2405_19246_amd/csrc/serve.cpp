@@ -137,7 +137,10 @@ struct mmot_server {
 
     void loop();
     int finish(std::vector<Slot> &slots, const std::vector<int> &fin, const std::vector<Result> &hR);
-    int tile_flag() const { return (cfg.opts.flags & MMOT_FLAG_TILES) ? F_TILES : 0; }
+    int tile_flag() const
+    {
+        return ((cfg.opts.flags & MMOT_FLAG_TILES) ? F_TILES : 0) | ((cfg.opts.flags & MMOT_FLAG_NO_GRAPH) ? F_NO_GRAPH : 0);
+    }
     int path_flag() const { return ((cfg.opts.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | tile_flag(); }
 };
 

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstring>
 #include <cmath>
 
@@ -149,23 +151,78 @@ Carve carve(int l, int ntile, int B)
     return c;
 }
 
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tune;  // (l, ceil(log2 N)) -> tile length picked by the autotuner
+
+int size_class(int64_t N)
+{
+    int c = 0;
+    while (((int64_t)1 << c) < N) ++c;
+    return c;
+}
+
+int rule_length(int64_t N, bool force)
+{
+    const int b = force ? pow2_ceil(std::sqrt((double)N)) : pow2_ceil(std::sqrt(8.0 * (double)N));
+    return std::max(force ? 8 : 64, std::min(b, 4096));
+}
+
 }  // namespace
 
 bool tile_shape(int l, int64_t N, int flags, int *ntile, int *B)
 {
     const bool force = (flags & F_TILES) != 0;
     if (!force && N < tile_min_n(l)) return false;
-    int b = force ? pow2_ceil(std::sqrt((double)N)) : pow2_ceil(std::sqrt(8.0 * (double)N));
-    b = std::max(force ? 8 : 64, std::min(b, 4096));
+    int b = rule_length(N, force);
+    if (!force) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find({l, size_class(N)});
+        if (it != g_tune.end()) b = it->second;
+    }
     *B = b;
     *ntile = (int)((N + b - 1) / b);
     return true;
 }
 
+int tile_candidates(int l, int64_t N, int flags, int *cand)
+{
+    const bool force = (flags & F_TILES) != 0;
+    if (!force && N < tile_min_n(l)) return 0;
+    const int b = rule_length(N, force);
+    if (force) {
+        cand[0] = b;
+        return 1;
+    }
+    int k = 0;
+    for (int c : {b / 2, b, 2 * b})
+        if (c >= 64 && c <= 8192) cand[k++] = c;
+    return k;
+}
+
+bool tile_tuned(int l, int64_t N)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune.count({l, size_class(N)}) != 0;
+}
+
+void tile_set_tuned(int l, int64_t N, int B)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[{l, size_class(N)}] = B;
+}
+
 size_t tile_scratch_bytes(int l, int64_t N, int ntile, int B)
 {
-    (void)N;
-    return carve(l, ntile, B).total;
+    // room for every length the autotuner may pick for this N
+    (void)ntile;
+    (void)B;
+    int cand[3];
+    const int k = tile_candidates(l, N, 0, cand);
+    size_t best = 0;
+    for (int i = 0; i < k; ++i) best = std::max(best, carve(l, (int)((N + cand[i] - 1) / cand[i]), cand[i]).total);
+    const int b = rule_length(N, true);
+    best = std::max(best, carve(l, (int)((N + b - 1) / b), b).total);
+    return best;
 }
 
 TileInst tile_inst(int l, int ntile, int B, char *scratch)

@@ -26,7 +26,15 @@ int64_t tile_min_n(int l);
 // Whether an instance is tiled, and its tile count and tile length B (positions).
 bool tile_shape(int l, int64_t N, int flags, int *ntile, int *B);
 
-// Scratch bytes of a tiled solve and its layout inside a scratch block.
+// Autotuner of the tile length: candidate lengths for an instance (0 if it is
+// not tiled), whether its (l, ceil(log2 N)) class has been measured, and the
+// measured choice (process-wide cache, read by tile_shape).
+int tile_candidates(int l, int64_t N, int flags, int *cand);
+bool tile_tuned(int l, int64_t N);
+void tile_set_tuned(int l, int64_t N, int B);
+
+// Scratch bytes of a tiled solve (room for every candidate length) and its
+// layout inside a scratch block.
 size_t tile_scratch_bytes(int l, int64_t N, int ntile, int B);
 TileInst tile_inst(int l, int ntile, int B, char *scratch);
 

@@ -28,6 +28,12 @@ size_t r256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 using namespace rt;
 
+#define TCHK(call)                                                                                      \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess) return fail(MMOT_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
 hipError_t tile_buffers_reserve(BatchBuffers *bb, size_t jobs_bytes)
 {
     if (jobs_bytes <= bb->jobs_cap) return hipSuccess;
@@ -85,16 +91,97 @@ const int *tile_group_list(const BatchBuffers *bb, const TileJobs &J)
     return reinterpret_cast<const int *>(bb->djobs + b1 + b2 + b3);
 }
 
-#define TCHK(call)                                                                                      \
-    do {                                                                                                \
-        hipError_t e_ = (call);                                                                         \
-        if (e_ != hipSuccess) return fail(MMOT_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
 
+
+// Autotuner of the tile length.  For an instance whose (l, ceil(log2 N)) class
+// has no measured length yet: its potentials are initialised as the solve would
+// (phi = 1/N unless warm), then one tiled FP64 check pass of marginal 0 runs at
+// each candidate length (the rule's, half and double; warm-up run, then a run
+// timed with HIP events on the stream), and the fastest is kept for the class.
+static int tune_tile_length(int l, int i, int count, const Inst *hI, const Ptrs *hP, const RunOpts &o, int flags,
+                            hipStream_t s, BatchBuffers *bb)
+{
+    int cand[3];
+    const int k = tile_candidates(l, hI[i].N, flags | hP[i].flags, cand);
+    if (k <= 1) {
+        if (k == 1) tile_set_tuned(l, hI[i].N, cand[0]);
+        return MMOT_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TCHK(hipEventCreate(&e0));
+    TCHK(hipEventCreate(&e1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } eg{e0, e1};
+    std::vector<TileInst> hti(count);
+    std::vector<char> jh;
+    int best = cand[0];
+    float best_ms = INFINITY;
+    for (int c = 0; c < k; ++c) {
+        const int B = cand[c];
+        const int nt = (int)((hI[i].N + B - 1) / B);
+        hti[i] = tile_inst(l, nt, B, reinterpret_cast<char *>(hP[i].scratch));
+        TCHK(hipMemcpyAsync(bb->dTI + i, &hti[i], sizeof(TileInst), hipMemcpyHostToDevice, s));
+        TileJobs J;
+        TCHK(upload_jobs(std::vector<int>{i}, hti, l, bb, s, jh, &J));
+        if (c == 0) TCHK(launch_tile_init(bb->dI, bb->dP, tile_group_list(bb, J), 1, o, s));
+        TCHK(launch_tile_pass(l, 0, P_CHECK, bb->dI, bb->dP, bb->dTI, nullptr, J, 0, 0, s));
+        TCHK(hipEventRecord(e0, s));
+        TCHK(launch_tile_pass(l, 0, P_CHECK, bb->dI, bb->dP, bb->dTI, nullptr, J, 0, 0, s));
+        TCHK(hipEventRecord(e1, s));
+        TCHK(hipStreamSynchronize(s));
+        float ms = 0.f;
+        TCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = B;
+        }
+    }
+    tile_set_tuned(l, hI[i].N, best);
+    return MMOT_OK;
+}
+
+static int tiled_group_solve_on(int l, const std::vector<int> &g, int count, const Inst *hI, const Ptrs *hP,
+                                int precision, const RunOpts &o, int flags, hipStream_t s, BatchBuffers *bb,
+                                Result *hR);
+
+// The legacy default stream cannot be captured into a graph, so the tiled loop
+// runs on a stream of the library's own (one per host thread, non-blocking,
+// default priority), ordered after the caller's stream by an event and before
+// its later work by another.
 int tiled_group_solve(int l, const std::vector<int> &g, int count, const Inst *hI, const Ptrs *hP, int precision,
                       const RunOpts &o, int flags, hipStream_t s, BatchBuffers *bb, Result *hR)
 {
     if (g.empty()) return MMOT_OK;
+    thread_local hipStream_t side = nullptr;
+    thread_local hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    if (!side) {
+        TCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        TCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+        TCHK(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+    }
+    TCHK(hipEventRecord(ev_in, s));
+    TCHK(hipStreamWaitEvent(side, ev_in, 0));
+    const int rc = tiled_group_solve_on(l, g, count, hI, hP, precision, o, flags, side, bb, hR);
+    TCHK(hipEventRecord(ev_out, side));
+    TCHK(hipStreamWaitEvent(s, ev_out, 0));
+    return rc;
+}
+
+static int tiled_group_solve_on(int l, const std::vector<int> &g, int count, const Inst *hI, const Ptrs *hP,
+                                int precision, const RunOpts &o, int flags, hipStream_t s, BatchBuffers *bb,
+                                Result *hR)
+{
+    for (int i : g)
+        if (!((flags | hP[i].flags) & F_TILES) && !tile_tuned(l, hI[i].N)) {
+            const int rc = tune_tile_length(l, i, count, hI, hP, o, flags, s, bb);
+            if (rc) return rc;
+        }
     std::vector<TileInst> hTI(count);
     std::vector<TileTrack> hTT(count);
     for (int i = 0; i < count; ++i) {
@@ -117,23 +204,62 @@ int tiled_group_solve(int l, const std::vector<int> &g, int count, const Inst *h
     const int *dlist = tile_group_list(bb, J);
     TCHK(launch_tile_init(bb->dI, bb->dP, dlist, (int)g.size(), o, s));
 
-    // sweeps in blocks; the host reads the states after each block
-    int block = 4;
+    // One sweep: l tiled updates, the estimate controller, l - 1 tiled FP64 checks (their jobs
+    // return at once unless the controller asked for a check), the stopping controller.
+    auto sweep = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int j = 0; j < l && e == hipSuccess; ++j)
+            e = launch_tile_pass(l, precision, P_UPDATE, bb->dI, bb->dP, bb->dTI, bb->dTT, J, j, TS_SWEEP, s);
+        if (e == hipSuccess) e = launch_tile_ctrl(l, 0, bb->dP, bb->dTI, bb->dTT, count, o, s);
+        for (int j = 0; j < l - 1 && e == hipSuccess; ++j)
+            e = launch_tile_pass(l, 0, P_CHECK, bb->dI, bb->dP, bb->dTI, bb->dTT, J, j, TS_CHECK, s);
+        if (e == hipSuccess) e = launch_tile_ctrl(l, 1, bb->dP, bb->dTI, bb->dTT, count, o, s);
+        return e;
+    };
+    // Sweeps in blocks of TILE_GRAPH_SWEEPS, captured once as a HIP graph and replayed (every
+    // launch of a block has the same arguments); the host reads the states after each block.
+    // Stopped instances' jobs return at once, so a block may run past an instance's stop.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const bool use_graph = !(flags & F_NO_GRAPH);
+    if (use_graph) {
+        TCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int rep = 0; rep < TILE_GRAPH_SWEEPS && e == hipSuccess; ++rep) e = sweep();
+        hipGraph_t gcap = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(s, &gcap);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (gcap) (void)hipGraphDestroy(gcap);
+            return fail(MMOT_ERR_HIP, std::string("capture of a sweep block: ") +
+                                          hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        graph = gcap;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(MMOT_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+    }
+    struct GraphGuard {
+        hipGraph_t g;
+        hipGraphExec_t x;
+        ~GraphGuard()
+        {
+            if (x) (void)hipGraphExecDestroy(x);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    } guard{graph, exec};
     for (;;) {
-        for (int rep = 0; rep < block; ++rep) {
-            for (int j = 0; j < l; ++j)
-                TCHK(launch_tile_pass(l, precision, P_UPDATE, bb->dI, bb->dP, bb->dTI, bb->dTT, J, j, TS_SWEEP, s));
-            TCHK(launch_tile_ctrl(l, 0, bb->dP, bb->dTI, bb->dTT, count, o, s));
-            for (int j = 0; j < l - 1; ++j)
-                TCHK(launch_tile_pass(l, 0, P_CHECK, bb->dI, bb->dP, bb->dTI, bb->dTT, J, j, TS_CHECK, s));
-            TCHK(launch_tile_ctrl(l, 1, bb->dP, bb->dTI, bb->dTT, count, o, s));
+        if (use_graph) {
+            TCHK(hipGraphLaunch(exec, s));
+        } else {
+            for (int rep = 0; rep < TILE_GRAPH_SWEEPS; ++rep) TCHK(sweep());
         }
         TCHK(hipMemcpyAsync(hTT.data(), bb->dTT, sizeof(TileTrack) * count, hipMemcpyDeviceToHost, s));
         TCHK(hipStreamSynchronize(s));
         bool any = false;
         for (int i : g) any |= hTT[i].state == TS_SWEEP || hTT[i].state == TS_CHECK;
         if (!any) break;
-        block = std::min(block * 2, 32);
     }
 
     // objective of the instances that finished cleanly

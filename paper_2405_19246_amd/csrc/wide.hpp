@@ -624,24 +624,74 @@ __global__ __launch_bounds__(64) void k_tile_agg(const Inst *I, const Ptrs *P, c
     tile_agg_job<L, E>(tm, &I[jb.x], TI[jb.x], P[jb.x].a, j, jb.y, jb.z, jb.w);
 }
 
+// acc + a b with the deferred normalisation of xmac_lazy (dual numbers: the
+// value part and the product rule for the cost-weighted part).
+template <typename M>
+__device__ __forceinline__ XF<M> chain_mac(XF<M> acc, XF<M> a, XF<M> b)
+{
+    return xmac_lazy(acc, a, b);
+}
+__device__ __forceinline__ DXF chain_mac(DXF acc, DXF a, DXF b)
+{
+    return {xmac_lazy(acc.v, a.v, b.v), xmac_lazy(xmac_lazy(acc.w, a.v, b.w), a.w, b.v)};
+}
+
+// The i-th subset of S in decreasing order (i = 0 is S itself): the bits of
+// 2^|S| - 1 - i dealt into the positions of S's members.
+__device__ __forceinline__ int nth_subset_desc(int S, int i)
+{
+    int x = (1 << popc(S)) - 1 - i, out = 0;
+    for (int b = 0, k = 0; b < 16; ++b)
+        if ((S >> b) & 1) out |= ((x >> k++) & 1) << b;
+    return out;
+}
+
+constexpr int CHAIN_THREADS = 512;
+
+// Number of work items of a hop over the subsets of n items.
+__host__ __device__ constexpr int chain_items(int n)
+{
+    int tot = 0;
+    for (int S = 0; S < (1 << n); ++S) tot += ((1 << __builtin_popcount(S)) + 32 - 1) / 32;
+    return tot;
+}
+constexpr int CHAIN_CHUNK = 32;  // subsets per work item
+
 // Carries from tile to tile in one direction, one workgroup per (instance,
 // direction).  In subset space (forward: S as held; backward: the complement of
 // the index), c_next(S) = sum_{S' subset S} c(S') Q_{|S'|}(S \ S') with c(empty) = 1.
+// The 3^(l-1) terms of a hop are dealt to the threads as work items of at most
+// CHAIN_CHUNK subsets of one S; each item's partial sum goes to LDS and a second
+// phase adds the items of each S.
 template <int L, typename E>
-__global__ __launch_bounds__(256) void k_tile_chain(const TileInst *TI, const TileTrack *Tr, const int2 *jobs,
-                                                   int njobs, int state_need)
+__global__ __launch_bounds__(CHAIN_THREADS) void k_tile_chain(const TileInst *TI, const TileTrack *Tr,
+                                                              const int2 *jobs, int njobs, int state_need)
 {
     using T_ = ET<E>;
     constexpr int D = WL<L, E>::D;
+    constexpr int n = L - 1;
+    // work items: S with 2^|S| subsets has ceil(2^|S| / CHAIN_CHUNK) of them
+    constexpr int MAXI = chain_items(n);
     __shared__ E c[D];
+    __shared__ E part[MAXI];
+    __shared__ int ioff[D + 1];
     const int2 jb = jobs[blockIdx.x];
     if (Tr && Tr[jb.x].state != state_need) return;
     const TileInst T = TI[jb.x];
     const int dir = jb.y;
     const int tid = threadIdx.x;
     auto idx = [&](int S) { return dir == 0 ? S : (D - 1) ^ S; };
+    if (tid == 0) {
+        int o = 0;
+        for (int S = 0; S < D; ++S) {
+            ioff[S] = o;
+            o += ((1 << popc(S)) + CHAIN_CHUNK - 1) / CHAIN_CHUNK;
+        }
+        ioff[D] = o;
+    }
     for (int S = tid; S < D; S += blockDim.x) c[S] = esel(S == 0, T_::one(), T_::zero());
     __syncthreads();
+    const int nitems = ioff[D];
     E *carry = reinterpret_cast<E *>(T.carry);
     const E *agg = reinterpret_cast<const E *>(T.agg);
     for (int s = 0; s < T.ntile; ++s) {
@@ -649,24 +699,30 @@ __global__ __launch_bounds__(256) void k_tile_chain(const TileInst *TI, const Ti
         for (int S = tid; S < D; S += blockDim.x) carry[((long)t * 2 + dir) * D + idx(S)] = c[S];
         if (s == T.ntile - 1) break;
         const E *q = agg + ((long)t * 2 + dir) * L * D;
-        E nv[(D + 255) / 256];
-#pragma unroll
-        for (int k = 0; k < (D + 255) / 256; ++k) {
-            const int S = tid + 256 * k;
-            if (S >= D) continue;
-            // S' runs over the subsets of S (S' = S first, the empty set last)
-            E acc = T_::zero();
-            for (int Sp = S;; Sp = (Sp - 1) & S) {
-                acc = T_::add(acc, T_::prod(c[Sp], q[(long)popc(Sp) * D + idx(S ^ Sp)]));
-                if (Sp == 0) break;
+        for (int it = tid; it < nitems; it += blockDim.x) {
+            // the item's state: the last S with ioff[S] <= it (binary search)
+            int lo = 0, hi = D - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (ioff[mid] <= it) lo = mid;
+                else hi = mid - 1;
             }
-            nv[k] = acc;
+            const int S = lo;
+            const int k0 = (it - ioff[S]) * CHAIN_CHUNK;
+            const int cnt = min(CHAIN_CHUNK, (1 << popc(S)) - k0);
+            int Sp = nth_subset_desc(S, k0);
+            E acc = T_::zero();
+            for (int k = 0; k < cnt; ++k) {
+                acc = chain_mac(acc, c[Sp], q[(long)popc(Sp) * D + idx(S ^ Sp)]);
+                Sp = (Sp - 1) & S;
+            }
+            part[it] = xnorm(acc);
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < (D + 255) / 256; ++k) {
-            const int S = tid + 256 * k;
-            if (S < D) c[S] = nv[k];
+        for (int S = tid; S < D; S += blockDim.x) {
+            E acc = part[ioff[S]];
+            for (int it = ioff[S] + 1; it < ioff[S + 1]; ++it) acc = T_::add(acc, part[it]);
+            c[S] = acc;
         }
         __syncthreads();
     }

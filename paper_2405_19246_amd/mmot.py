@@ -21,6 +21,7 @@ FP64, FP32 = 0, 1
 FLAG_WARM_START = 1
 FLAG_NO_FAST = 2
 FLAG_TILES = 4
+FLAG_NO_GRAPH = 8
 MAX_L = 10
 
 _c_d, _c_i32, _c_i64, _c_p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
@@ -143,8 +144,9 @@ def _stream_handle(stream) -> int:
     return int(s.cuda_stream)
 
 
-def _flags(warm_start: bool, fast: bool, tiles: bool = False) -> int:
-    return (FLAG_WARM_START if warm_start else 0) | (0 if fast else FLAG_NO_FAST) | (FLAG_TILES if tiles else 0)
+def _flags(warm_start: bool, fast: bool, tiles: bool = False, graph: bool = True) -> int:
+    return ((FLAG_WARM_START if warm_start else 0) | (0 if fast else FLAG_NO_FAST) | (FLAG_TILES if tiles else 0) |
+            (0 if graph else FLAG_NO_GRAPH))
 
 
 def _dev_f64(t, shape, name):
@@ -163,11 +165,11 @@ class Plan:
 
     def __init__(self, l: int, N: int, h: float, eps: float, precision: int = FP64, tol: float = 1e-8,
                  itr_max: int = 1000, check_every: int = 10, warm_start: bool = False, stream=None,
-                 fast: bool = True, tiles: bool = False):
+                 fast: bool = True, tiles: bool = False, graph: bool = True):
         self.l, self.N, self.h, self.eps, self.precision = int(l), int(N), float(h), float(eps), int(precision)
         self.stream = stream
         p = Problem(self.l, self.N, self.h, self.eps, self.precision)
-        o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast, tiles))
+        o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast, tiles, graph))
         h_ = _c_p()
         _check(lib().mmot_plan(ctypes.byref(p), ctypes.byref(o), _c_p(_stream_handle(stream)), ctypes.byref(h_)))
         self._h = h_
@@ -260,7 +262,7 @@ def last_batch_timing() -> dict:
 
 def solve_batch(instances: Sequence[dict], precision: int = FP32, tol: float = 1e-6, itr_max: int = 100000,
                 check_every: int = 10, warm_start: bool = False, stream=None, fast: bool = True,
-                tiles: bool = False) -> list:
+                tiles: bool = False, graph: bool = True) -> list:
     """mmot_solve_batch: instances are dicts with l, N, h, eps, log_u, log_phi (device tensors).
 
     fast=False sets MMOT_FLAG_NO_FAST (every solve on the extended-range solver); tiles=True sets
@@ -271,7 +273,7 @@ def solve_batch(instances: Sequence[dict], precision: int = FP32, tol: float = 1
         pu = _dev_f64(d["log_u"], (d["l"], d["N"]), "log_u")
         pa = _dev_f64(d["log_phi"], (d["l"], d["N"]), "log_phi")
         arr[i] = Instance(int(d["l"]), int(d["N"]), float(d["h"]), float(d["eps"]), pu, pa)
-    o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast, tiles))
+    o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast, tiles, graph))
     res = (Result * max(n, 1))()
     _check(lib().mmot_solve_batch(arr, n, int(precision), ctypes.byref(o), _c_p(_stream_handle(stream)), res),
            allow=(OK, NOT_CONVERGED))

@@ -169,3 +169,22 @@ def test_tiled_batch_fp32_certified():
         assert err[:-1].sum() <= 1e-6, (d["l"], d["N"], err)
         ref = fastcheck.objective(d["log_phi"].cpu().numpy(), d["h"], d["eps"])
         assert abs(r["W"] - ref) <= 1e-10 * abs(ref), (d["l"], d["N"])
+
+
+def test_graph_replay_equals_eager_launches():
+    # the tiled sweeps replayed as captured graphs of 8-sweep blocks give the same
+    # iterates, bit for bit, as the same launches issued one by one; several
+    # replays with host reads between them are covered (the solve takes > 8 sweeps)
+    mmot = _mmot()
+    l, N, eps = 3, 20000, 0.05
+    u = inputs.marginals(l, N, K=3, master_seed=12, instance=1)
+    out = []
+    for graph in (True, False, True):
+        d = dict(l=l, N=N, h=inputs.grid_step(N), eps=eps, log_u=to_dev(np.log(u)), log_phi=to_dev(np.zeros((l, N))))
+        say("tiled solve, graph=%s" % graph)
+        r = mmot.solve_batch([d], precision=mmot.FP64, tol=1e-9, itr_max=300, check_every=0, graph=graph)[0]
+        out.append((d["log_phi"].cpu().numpy(), r))
+    for a, r in out[1:]:
+        assert np.array_equal(a, out[0][0])
+        assert r["iters"] == out[0][1]["iters"] and r["W"] == out[0][1]["W"]
+    assert out[0][1]["iters"] > 16, out[0][1]
