@@ -82,7 +82,9 @@ typedef struct {
  * the extended-range solver (one wavefront per solve) instead of the
  * register-resident one (one workgroup per solve, taken when N fits it);
  * MMOT_FLAG_TILES cuts every instance into tiles (otherwise only long ones:
- * N >= 16384 for l <= 6, N >= 4096 for l >= 7); MMOT_FLAG_NO_GRAPH launches
+ * N >= 16384 for l <= 6, N >= 4096 for l >= 7, or, in a batch with fewer than
+ * 512 instances off the register-resident path, every such instance from
+ * N = 256 up; not with MMOT_FLAG_NO_FAST); MMOT_FLAG_NO_GRAPH launches
  * the tiled sweeps one by one instead of replaying a captured HIP graph of a
  * block of sweeps (same iterates, bit for bit). */
 typedef struct {

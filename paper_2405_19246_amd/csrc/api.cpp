@@ -466,7 +466,7 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
                  Result *hR, BatchBuffers *bb, bool timed)
 {
     if (count <= 0) return MMOT_OK;
-    const int flags = o.flags;
+    int flags = o.flags;
     std::vector<double> cost(count);
     for (int i = 0; i < count; ++i) cost[i] = est_cost(hI[i].l, hI[i].N, hI[i].h / hI[i].hoe);
     auto by_cost = [&](std::vector<int> &v) {
@@ -476,13 +476,25 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     // (l <= 4, N fits a workgroup), one wavefront per instance (the rest).  Index p
     // of robust / wide / tiled is the precision of the instance's scans: FP32 mode
     // keeps FP32 mantissas only where the scan window is short (scan_precision).
+    // A batch with few instances that the register-resident path does not take cannot fill the
+    // GPU with one team or wavefront per instance: then every such instance from N = 256 up is
+    // tiled (its scratch always has room for both layouts, scratch_bytes).
+    {
+        int n_slow = 0;
+        for (int i = 0; i < count; ++i)
+            if ((flags & F_NO_FAST) || !fast_eligible(hI[i], precision)) ++n_slow;
+        // (MMOT_FLAG_NO_FAST asks for the one-wavefront solver: no small-batch tiling then)
+        if (n_slow < SMALL_BATCH && !(flags & F_NO_FAST)) flags |= F_TILE_SMALL;
+    }
     std::vector<int> robust[2], group[MAXL + 1], wide[MAXL + 1][2], tiled[MAXL + 1][2];
     for (int i = 0; i < count; ++i) {
         int nt = 0, tb = 0;
         const int p = scan_precision(hI[i], precision);
-        if (tile_shape(hI[i].l, hI[i].N, flags | hP[i].flags, &nt, &tb)) tiled[hI[i].l][p].push_back(i);
+        const int fl = flags | hP[i].flags;
+        const bool fast = !(fl & F_NO_FAST) && !(fl & F_TILES) && fast_eligible(hI[i], precision);
+        if (fast) group[hI[i].l].push_back(i);
+        else if (tile_shape(hI[i].l, hI[i].N, fl, &nt, &tb)) tiled[hI[i].l][p].push_back(i);
         else if (hI[i].l >= WIDE_MINL) wide[hI[i].l][p].push_back(i);
-        else if (!(flags & F_NO_FAST) && fast_eligible(hI[i], precision)) group[hI[i].l].push_back(i);
         else robust[p].push_back(i);
     }
     // dorder: [robust FP64 | robust FP32 | wide (l, p) ... | group 2 | group 3 | ...], then the second

@@ -121,6 +121,9 @@ constexpr int32_t F_NO_FAST = 8;     // host only: every instance on the extende
 constexpr int32_t F_TILES = 16;      // host only: every instance is tiled (tests and small shapes)
 constexpr int32_t F_VALIDATE = 32;   // host only: check the marginals before solving
 constexpr int32_t F_NO_GRAPH = 64;   // host only: tiled sweep blocks launched one by one, not as a graph
+constexpr int32_t F_TILE_SMALL = 128; // host only: tile from N = TILE_SMALL_N (a batch too small to fill the GPU)
+constexpr int TILE_SMALL_N = 256;     // shortest tiled instance in a small batch
+constexpr int SMALL_BATCH = 512;      // fewer instances off the register-resident path than this: small batch
 constexpr int TILE_GRAPH_SWEEPS = 8; // sweeps per captured block of a tiled solve
 
 // Lane width V per (l, pass kind) -- trades registers against scan overhead.

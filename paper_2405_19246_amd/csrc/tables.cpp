@@ -76,9 +76,12 @@ int64_t tile_min_n(int l)
 
 size_t scratch_bytes(int l, int64_t N, int precision, int flags)
 {
+    // room for the untiled passes and, from N = TILE_SMALL_N up, for every tiled layout the batch
+    // host or the autotuner may pick
     int nt = 0, B = 0;
-    if (tile_shape(l, N, flags, &nt, &B)) return tile_scratch_bytes(l, N, nt, B);
-    return pass_scratch_bytes(l, N, precision);
+    size_t b = pass_scratch_bytes(l, N, precision);
+    if (tile_shape(l, N, flags | F_TILE_SMALL, &nt, &B)) b = std::max(b, tile_scratch_bytes(l, N, nt, B));
+    return b;
 }
 
 size_t pass_scratch_bytes(int l, int64_t N, int precision)
@@ -172,7 +175,7 @@ int rule_length(int64_t N, bool force)
 bool tile_shape(int l, int64_t N, int flags, int *ntile, int *B)
 {
     const bool force = (flags & F_TILES) != 0;
-    if (!force && N < tile_min_n(l)) return false;
+    if (!force && N < ((flags & F_TILE_SMALL) ? (int64_t)TILE_SMALL_N : tile_min_n(l))) return false;
     int b = rule_length(N, force);
     if (!force) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -187,7 +190,7 @@ bool tile_shape(int l, int64_t N, int flags, int *ntile, int *B)
 int tile_candidates(int l, int64_t N, int flags, int *cand)
 {
     const bool force = (flags & F_TILES) != 0;
-    if (!force && N < tile_min_n(l)) return 0;
+    if (!force && N < ((flags & F_TILE_SMALL) ? (int64_t)TILE_SMALL_N : tile_min_n(l))) return 0;
     const int b = rule_length(N, force);
     if (force) {
         cand[0] = b;
@@ -217,7 +220,7 @@ size_t tile_scratch_bytes(int l, int64_t N, int ntile, int B)
     (void)ntile;
     (void)B;
     int cand[3];
-    const int k = tile_candidates(l, N, 0, cand);
+    const int k = tile_candidates(l, N, F_TILE_SMALL, cand);
     size_t best = 0;
     for (int i = 0; i < k; ++i) best = std::max(best, carve(l, (int)((N + cand[i] - 1) / cand[i]), cand[i]).total);
     const int b = rule_length(N, true);
