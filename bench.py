@@ -228,7 +228,7 @@ def l10_shape(dev, sweeps: int):
     mmot.solve_batch(d, precision=mmot.FP32, tol=-1.0, itr_max=1, check_every=0)
     res, dt = timed(lambda: mmot.solve_batch(d, precision=mmot.FP32, tol=-1.0, itr_max=sweeps, check_every=0))
     return dict(value=units_of(res) / dt, sweeps=sweeps, seconds=dt, ms_per_sweep=dt / sweeps * 1e3,
-                Res_after=res[0]["marg_err"], path="tiled (teams of 64 lanes, 8 FP32 states each)")
+                Res_after=res[0]["marg_err"], path="tiled (teams of 64 lanes, 8 states each, FP64 mantissas)")
 
 
 def c4_batch(dev, count: int, itr_max: int):

@@ -489,13 +489,12 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
     std::vector<int> robust[2], group[MAXL + 1], wide[MAXL + 1][2], tiled[MAXL + 1][2];
     for (int i = 0; i < count; ++i) {
         int nt = 0, tb = 0;
-        const int p = scan_precision(hI[i], precision);
         const int fl = flags | hP[i].flags;
         const bool fast = !(fl & F_NO_FAST) && !(fl & F_TILES) && fast_eligible(hI[i], precision);
         if (fast) group[hI[i].l].push_back(i);
-        else if (tile_shape(hI[i].l, hI[i].N, fl, &nt, &tb)) tiled[hI[i].l][p].push_back(i);
-        else if (hI[i].l >= WIDE_MINL) wide[hI[i].l][p].push_back(i);
-        else robust[p].push_back(i);
+        else if (tile_shape(hI[i].l, hI[i].N, fl, &nt, &tb)) tiled[hI[i].l][scan_precision(hI[i], precision, true)].push_back(i);
+        else if (hI[i].l >= WIDE_MINL) wide[hI[i].l][scan_precision(hI[i], precision, true)].push_back(i);
+        else robust[scan_precision(hI[i], precision, false)].push_back(i);
     }
     // dorder: [robust FP64 | robust FP32 | wide (l, p) ... | group 2 | group 3 | ...], then the second
     // half for resumed and objective lists

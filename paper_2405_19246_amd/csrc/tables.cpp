@@ -98,14 +98,14 @@ size_t pass_scratch_bytes(int l, int64_t N, int precision)
     return (best + 255) & ~(size_t)255;
 }
 
-int scan_precision(const Inst &I, int precision)
+int scan_precision(const Inst &I, int precision, bool team_layout)
 {
     if (precision != MMOT_FP32) return MMOT_FP64;
     // the slowest-decaying state takes g = lambda^(l-1) per position; a scan then
     // sums about 1 / (1 - g) positions of comparable terms, and FP32 rounding of
     // that many steps stays below ~1e-7 relative only for short windows
     const double window = 1.0 / -std::expm1(-(double)(I.l - 1) * I.hoe);
-    return window <= FP32_MAX_WINDOW ? MMOT_FP32 : MMOT_FP64;
+    return window <= (team_layout ? FP32_MAX_WINDOW_TEAM : FP32_MAX_WINDOW) ? MMOT_FP32 : MMOT_FP64;
 }
 
 bool fast_eligible(const Inst &I, int precision)

@@ -39,11 +39,16 @@ size_t tile_scratch_bytes(int l, int64_t N, int ntile, int B);
 TileInst tile_inst(int l, int ntile, int B, char *scratch);
 
 // Mantissa precision of the scans of an instance solved in `precision`: FP32
-// mode keeps FP32 mantissas where the scan window 1 / (1 - lambda^(l-1)) is at
-// most FP32_MAX_WINDOW positions and takes FP64 mantissas beyond (the same VALU
-// rate on this GPU without packed FP32; only registers and memory double).
+// mode keeps FP32 mantissas on the one-wavefront solver (block floating point)
+// where the scan window 1 / (1 - lambda^(l-1)) is at most FP32_MAX_WINDOW
+// positions, and FP64 mantissas beyond.  The team and tiled layouts take FP64
+// mantissas in FP32 mode (FP32_MAX_WINDOW_TEAM = 0): their FP32 iterations
+// settled about 1e-6 relative away from the FP64 fixed point (l = 5, N = 1000,
+// eps = 0.02, window 5.5: Res never below 1e-6).  On this GPU without packed
+// FP32 both run at the same VALU rate; only registers and memory double.
 constexpr double FP32_MAX_WINDOW = 64.0;
-int scan_precision(const Inst &I, int precision);
+constexpr double FP32_MAX_WINDOW_TEAM = 0.0;
+int scan_precision(const Inst &I, int precision, bool team_layout);
 
 // Whether the register-resident path (fast.hpp) takes an instance: its N fits
 // one workgroup of the sweep and of the FP64 check kernel, and the discount
