@@ -15,6 +15,10 @@ Recipe (stands in for the paper's synthetic 1-D workloads of Sec. 5.1/5.2):
     distribution (``uniform_frac``);
   * marginal q of instance s draws from numpy PCG64 seeded with the
     sequence (master_seed, s, q), so every marginal is reproducible alone.
+
+The Ricker workload of Sec. 5.2 is deterministic (``ricker_marginals``): N
+uniform points on [-2, 2], three wavelets shifted by tau, squared and
+normalised with the floor delta of that section.
 """
 from __future__ import annotations
 
@@ -60,6 +64,34 @@ def uniform_random_marginals(l: int, N: int, seed: int = 0) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     u = rng.uniform(0.0, 1.0, size=(l, N))
     return u / u.sum(axis=1, keepdims=True)
+
+
+def ricker_grid(N: int):
+    """(t, h): N uniform points on [-2, 2] and their step (Sec. 5.2)."""
+    t = np.linspace(-2.0, 2.0, N)
+    return t, (4.0 / (N - 1) if N > 1 else 1.0)
+
+
+def ricker(t: np.ndarray, A: float = 1.0, F0: float = 1.0) -> np.ndarray:
+    """Ricker wavelet A (1 - 2 pi^2 F0^2 t^2) exp(-pi^2 F0^2 t^2) (Sec. 5.2)."""
+    z = (np.pi * F0 * t) ** 2
+    return A * (1.0 - 2.0 * z) * np.exp(-z)
+
+
+def ricker_marginals(N: int, taus=(0.0, 0.75, 1.5), delta: float = 1e-3) -> np.ndarray:
+    """Array [len(taus), N]: marginal q is (f_q^2 / |f_q^2|_1 + delta) / (1 + N delta).
+
+    f_q(t) = R(t - tau_q) on the grid of ``ricker_grid`` with A = F0 = 1.  The
+    1-norm is the plain sum over the nodes and the normalising constant in
+    the denominator is N, so each row sums to 1 (Sec. 5.2's squared-signal
+    normalisation with a floor, read on the discrete grid).
+    """
+    t, _ = ricker_grid(N)
+    out = []
+    for tau in taus:
+        f2 = ricker(t - tau) ** 2
+        out.append((f2 / f2.sum() + delta) / (1.0 + N * delta))
+    return np.stack(out)
 
 
 # Named workloads.  Each entry: l, N, K, eps, floor, uniform_frac.

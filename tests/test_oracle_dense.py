@@ -179,15 +179,8 @@ def test_linear_domain_breaks_where_log_domain_does_not():
     # eps = 1e-3 (Sec. 5.2, at its 89th iteration; the exact count depends on the
     # overflow test and is not pinned); the log-domain iteration stays finite.
     N = 100
-    t = np.linspace(-2.0, 2.0, N)
-    h = t[1] - t[0]
-    rick = lambda tt: (1 - 2 * np.pi ** 2 * tt ** 2) * np.exp(-np.pi ** 2 * tt ** 2)  # noqa: E731
-    delta = 1e-3
-    u = []
-    for tau in (0.0, 0.75, 1.5):
-        f2 = rick(t - tau) ** 2
-        u.append((f2 / f2.sum() + delta) / (1 + N * delta))
-    u = np.array(u)
+    u = inputs.ricker_marginals(N)
+    _, h = inputs.ricker_grid(N)
     lin = dense.sinkhorn_linear(u, h, 1e-3, itmax=200)
     assert lin["failed_at"] is not None
     r = dense.sinkhorn(u, h, 1e-3, itmax=lin["failed_at"] + 5, check_every=1000)

@@ -86,3 +86,23 @@ def test_fast_and_dense_plans_agree_like_the_paper(N):
     assert np.linalg.norm((P_O - P_S).ravel()) < 1e-14
     # one factor h in the objective: <varphi, FTVP-2(phi, psi)> is <C, T>
     assert abs(W_fast - r["W"]) < 1e-13
+
+
+def test_ricker_inputs_follow_sec_5_2():
+    # R(0) = A; R vanishes at t = +-1 / (sqrt(2) pi F0); each marginal sums to 1,
+    # sits at or above its floor delta / (1 + N delta) and peaks at the grid
+    # point nearest its shift tau once the grid resolves the main lobe (|R| is 1
+    # there, 2 e^{-3/2} on the side lobes)
+    assert inputs.ricker(np.array([0.0]))[0] == 1.0
+    r0 = 1.0 / (np.sqrt(2.0) * np.pi)
+    assert np.all(np.abs(inputs.ricker(np.array([-r0, r0]))) < 1e-15)
+    assert abs(inputs.ricker(np.array([np.sqrt(1.5) / np.pi]))[0] + 2 * np.exp(-1.5)) < 1e-15
+    for N in (97, 161, 401):
+        t, h = inputs.ricker_grid(N)
+        assert t[0] == -2.0 and t[-1] == 2.0 and abs(h - (t[1] - t[0])) < 1e-15
+        u = inputs.ricker_marginals(N)
+        assert u.shape == (3, N)
+        np.testing.assert_allclose(u.sum(axis=1), 1.0, rtol=1e-14)
+        assert np.all(u >= 1e-3 / (1 + N * 1e-3) * (1 - 1e-14))
+        for q, tau in enumerate((0.0, 0.75, 1.5)):
+            assert abs(t[np.argmax(u[q])] - tau) < 1e-12
