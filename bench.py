@@ -20,7 +20,8 @@ traffic is attached while the kernel sources match the profiled ones.
 
 Extra fields (skipped with --no-extras): the same batch in FP64 to 1e-8; the
 plain configuration (l = 3, N = 64, eps = 0.1, 500 FP64 sweeps, 10 seeds); the
-l = 10, N = 1e5, eps = 1e-3 shape (a few tiled sweeps); the batch on the
+l = 10, N = 1e5, eps = 1e-3 shape (a few tiled sweeps); the Ricker-wavelet
+problem (Table 2's sizes, time to each marginal error at N = 80); the batch on the
 one-wavefront solver; one solve per call; continuous-batching serving runs
 (the headline shape, and the mixed request stream with l up to 16 and N up to
 1e6, cancelled after a fixed window); the oracle timed on the host cores.
@@ -231,6 +232,31 @@ def l10_shape(dev, sweeps: int):
                 Res_after=res[0]["marg_err"], path="tiled (teams of 64 lanes, 8 states each, FP64 mantissas)")
 
 
+def ricker(dev):
+    """The Ricker-wavelet problem (three squared, floored wavelets on [-2, 2]), one FP64 solve per call.
+
+    table2: 100 sweeps at eps = 0.1 for N = 10 ... 160 (wall seconds of one call);
+    fig2a: N = 80, eps = 0.1 and 0.05, wall seconds and sweeps to reach each
+    marginal error (the residual checked after every sweep)."""
+    import torch
+    from paper_2405_19246_amd import inputs, mmot
+
+    def run(N, eps, tol, itr_max, check_every):
+        u = inputs.ricker_marginals(N)
+        _, h = inputs.ricker_grid(N)
+        lu = torch.tensor(np.log(u), dtype=torch.float64, device=dev)
+        plan = mmot.Plan(3, N, h, eps, precision=mmot.FP64, tol=tol, itr_max=itr_max, check_every=check_every)
+        plan.solve(lu)
+        (lp, r), dt = timed(lambda: plan.solve(lu))
+        return dict(seconds=dt, sweeps=r["iters"], Res=r["marg_err"], W=r["W"])
+
+    table2 = {str(N): run(N, 0.1, -1.0, 100, 0) for N in (10, 20, 40, 80, 160)}
+    fig2a = {}
+    for eps in (0.1, 0.05):
+        fig2a[str(eps)] = {"%.0e" % tol: run(80, eps, tol, 100000, 1) for tol in (1e-3, 1e-5, 1e-7, 1e-9)}
+    return {"table2_eps0.1_100_sweeps": table2, "fig2a_n80": fig2a}
+
+
 def c4_batch(dev, count: int, itr_max: int):
     import torch
     from paper_2405_19246_amd import inputs, mmot
@@ -333,7 +359,7 @@ def main():
     ap.add_argument("--c4", type=int, default=0, metavar="COUNT",
                     help="also solve the first COUNT instances of the mixed batch configuration")
     ap.add_argument("--c4-itr-max", type=int, default=100000)
-    ap.add_argument("--only", choices=("plain", "l10", "serve_mixed"),
+    ap.add_argument("--only", choices=("plain", "l10", "serve_mixed", "ricker"),
                     help="run only this extra leg and print its JSON (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 4 times (reference for HBM byte counters)")
@@ -368,7 +394,7 @@ def main():
     mmot.lib()
     if args.only:
         leg = {"plain": lambda: plain_config(dev), "l10": lambda: l10_shape(dev, 3),
-               "serve_mixed": lambda: serve_mixed(0.5, 8.0)}[args.only]()
+               "serve_mixed": lambda: serve_mixed(0.5, 8.0), "ricker": lambda: ricker(dev)}[args.only]()
         print(json.dumps({"leg": args.only, **leg}), flush=True)
         return
     tol32, tol64 = 1e-6, 1e-8
@@ -447,6 +473,7 @@ def main():
                            kernel_ms=mmot.last_batch_kernel_ms())
         out["plain_config"] = plain_config(dev)
         out["l10_n100000_eps0.001"] = l10_shape(dev, 3)
+        out["ricker"] = ricker(dev)
         (rx, tx) = timed(lambda: step(mmot.FP32, tol32, fast=False))
         out["one_wavefront_solver"] = dict(value=units_of(rx) / tx, seconds=tx,
                                            all_converged=all(r["status"] == 0 for r in rx),

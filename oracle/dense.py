@@ -4,7 +4,10 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 Everything here forms the full N^l tensors and follows the paper's definitions:
   * cost on a uniform mesh of step h:  c(i_1..i_l) = h * sum_{p<q} |i_p - i_q|
-    (Sec. 3 for l = 3, Sec. 4.2 for general l);
+    (Sec. 3 for l = 3, Sec. 4.2 for general l); on a non-uniform mesh of
+    coordinates x (Sec. 3 notes that the method carries over to one):
+    c(i_1..i_l) = sum_{p<q} |x[i_p] - x[i_q]|, every marginal on the same x
+    (marginals with smaller supports carry zeros on the other points);
   * Gibbs kernel K = exp(-c / eps) = lambda^{sum |i_p - i_q|}, lambda = exp(-h/eps)
     (Sec. 2, Eq. for K; Sec. 4.2);
   * Gibbs form of the plan t = K * prod_q phi_q(i_q) (Sec. 2 Eq. T value; Sec. 4.2);
@@ -43,8 +46,23 @@ def cost_tensor(l: int, N: int, h: float) -> np.ndarray:
     return h * cost_exponent(l, N).astype(np.float64)
 
 
-def log_kernel(l: int, N: int, h: float, eps: float) -> np.ndarray:
-    """log K = -C / eps.  h = 0 gives lambda = 1; eps = 0 is not allowed."""
+def cost_tensor_grid(l: int, x: np.ndarray) -> np.ndarray:
+    """C[i_1..i_l] = sum_{p<q} |x[i_p] - x[i_q]| on coordinates x (shape (N,)*l)."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    pts = [x.reshape((1,) * p + (N,) + (1,) * (l - 1 - p)) for p in range(l)]
+    C = np.zeros((N,) * l)
+    for p in range(l):
+        for q in range(p + 1, l):
+            C = C + np.abs(pts[p] - pts[q])
+    return C
+
+
+def log_kernel(l: int, N: int, h: float, eps: float, x=None) -> np.ndarray:
+    """log K = -C / eps.  h = 0 gives lambda = 1; eps = 0 is not allowed.
+    x: grid coordinates (then h is unused)."""
+    if x is not None:
+        return -cost_tensor_grid(l, x) / eps
     return -(h / eps) * cost_exponent(l, N).astype(np.float64)
 
 
@@ -114,23 +132,25 @@ def residual(logK: np.ndarray, log_phi: np.ndarray, u: np.ndarray) -> float:
     return r
 
 
-def objective(l: int, N: int, h: float, eps: float, log_phi: np.ndarray) -> float:
+def objective(l: int, N: int, h: float, eps: float, log_phi: np.ndarray, x=None) -> float:
     """W_eps = <C, T> (Sec. 2 Eq. mmot distance, no entropy term)."""
-    logK = log_kernel(l, N, h, eps)
+    logK = log_kernel(l, N, h, eps, x)
     T = np.exp(log_plan(logK, log_phi))
-    return float(np.sum(cost_tensor(l, N, h) * T))
+    C = cost_tensor_grid(l, x) if x is not None else cost_tensor(l, N, h)
+    return float(np.sum(C * T))
 
 
 def sinkhorn(u: np.ndarray, h: float, eps: float, itmax: int, tol: float = 0.0,
-             check_every: int = 1, log_phi0: np.ndarray | None = None) -> dict:
+             check_every: int = 1, log_phi0: np.ndarray | None = None, x=None) -> dict:
     """Generalised Gauss-Seidel Sinkhorn in the log domain (Alg. 1 for l marginals).
 
     u: [l, N] marginals.  Runs at most itmax sweeps; after every check_every-th
     sweep computes Res and stops once Res <= tol (tol = 0 runs all itmax).
-    Returns dict(log_phi, W, iters, res, res_hist).
+    x: grid coordinates (non-uniform mesh).  Returns dict(log_phi, W, iters,
+    res, res_hist).
     """
     l, N = u.shape
-    logK = log_kernel(l, N, h, eps)
+    logK = log_kernel(l, N, h, eps, x)
     with np.errstate(divide="ignore"):
         log_u = np.log(u)
     a = np.full((l, N), -np.log(N)) if log_phi0 is None else np.array(log_phi0, dtype=np.float64)
@@ -144,7 +164,7 @@ def sinkhorn(u: np.ndarray, h: float, eps: float, itmax: int, tol: float = 0.0,
         if it % check_every == 0 or it == itmax:
             res = residual(logK, a, u)
             hist.append((it, res))
-    W = objective(l, N, h, eps, a)
+    W = objective(l, N, h, eps, a, x)
     return dict(log_phi=a, W=W, iters=it, res=res, res_hist=hist)
 
 

@@ -1,7 +1,8 @@
 """ctypes loader for oracle/fastcheck.c.  TEST INFRASTRUCTURE ONLY.
 
 build() compiles the C file with gcc into oracle/_fastcheck.so; load() returns a
-small wrapper.  Arrays are float64, C-contiguous, shape [l, N].
+small wrapper.  Arrays are float64, C-contiguous, shape [l, N].  x (optional):
+non-decreasing grid coordinates [N] shared by the marginals; h is then unused.
 """
 from __future__ import annotations
 
@@ -32,10 +33,10 @@ def _load():
             build(force=True)
         lib = ctypes.CDLL(_SO)
         d, l_, i, p = ctypes.c_double, ctypes.c_long, ctypes.c_int, ctypes.c_void_p
-        lib.fc_marginal_product.argtypes = [i, l_, d, d, p, i, p]
-        lib.fc_objective.argtypes = [i, l_, d, d, p, p]
-        lib.fc_marginal_errors.argtypes = [i, l_, d, d, p, p, p]
-        lib.fc_sinkhorn.argtypes = [i, l_, d, d, p, p, l_, d, l_, p, p]
+        lib.fc_marginal_product.argtypes = [i, l_, d, d, p, p, i, p]
+        lib.fc_objective.argtypes = [i, l_, d, d, p, p, p]
+        lib.fc_marginal_errors.argtypes = [i, l_, d, d, p, p, p, p]
+        lib.fc_sinkhorn.argtypes = [i, l_, d, d, p, p, p, l_, d, l_, p, p]
         for f in (lib.fc_marginal_product, lib.fc_objective, lib.fc_marginal_errors, lib.fc_sinkhorn):
             f.restype = i
         _lib = lib
@@ -46,49 +47,63 @@ def _c(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def marginal_product_log(log_phi: np.ndarray, j: int, h: float, eps: float) -> np.ndarray:
+def _grid(x, N):
+    """(array kept alive, pointer) for optional coordinates."""
+    if x is None:
+        return None, None
+    g = _c(x)
+    if g.shape != (N,):
+        raise ValueError("grid must have N entries")
+    return g, g.ctypes.data
+
+
+def marginal_product_log(log_phi: np.ndarray, j: int, h: float, eps: float, x=None) -> np.ndarray:
     lib = _load()
     a = _c(log_phi)
     l, N = a.shape
+    g, gp = _grid(x, N)
     out = np.empty(N)
-    rc = lib.fc_marginal_product(l, N, h, eps, a.ctypes.data, j, out.ctypes.data)
+    rc = lib.fc_marginal_product(l, N, h, eps, gp, a.ctypes.data, j, out.ctypes.data)
     if rc:
         raise RuntimeError("fc_marginal_product failed: %d" % rc)
     return out
 
 
-def objective(log_phi: np.ndarray, h: float, eps: float) -> float:
+def objective(log_phi: np.ndarray, h: float, eps: float, x=None) -> float:
     lib = _load()
     a = _c(log_phi)
     l, N = a.shape
+    g, gp = _grid(x, N)
     W = ctypes.c_double()
-    rc = lib.fc_objective(l, N, h, eps, a.ctypes.data, ctypes.byref(W))
+    rc = lib.fc_objective(l, N, h, eps, gp, a.ctypes.data, ctypes.byref(W))
     if rc:
         raise RuntimeError("fc_objective failed: %d" % rc)
     return W.value
 
 
-def marginal_errors(u: np.ndarray, log_phi: np.ndarray, h: float, eps: float) -> np.ndarray:
+def marginal_errors(u: np.ndarray, log_phi: np.ndarray, h: float, eps: float, x=None) -> np.ndarray:
     lib = _load()
     a, uu = _c(log_phi), _c(u)
     l, N = a.shape
+    g, gp = _grid(x, N)
     err = np.empty(l)
-    rc = lib.fc_marginal_errors(l, N, h, eps, uu.ctypes.data, a.ctypes.data, err.ctypes.data)
+    rc = lib.fc_marginal_errors(l, N, h, eps, gp, uu.ctypes.data, a.ctypes.data, err.ctypes.data)
     if rc:
         raise RuntimeError("fc_marginal_errors failed: %d" % rc)
     return err
 
 
 def sinkhorn(u: np.ndarray, h: float, eps: float, itmax: int, tol: float = 0.0,
-             check_every: int = 1, log_phi0: np.ndarray | None = None) -> dict:
+             check_every: int = 1, log_phi0: np.ndarray | None = None, x=None) -> dict:
     lib = _load()
     uu = _c(u)
     l, N = uu.shape
+    g, gp = _grid(x, N)
     a = np.full((l, N), -np.log(N)) if log_phi0 is None else _c(log_phi0).copy()
     iters = ctypes.c_long()
     res = ctypes.c_double()
-    rc = lib.fc_sinkhorn(l, N, h, eps, uu.ctypes.data, a.ctypes.data, itmax, tol, check_every,
+    rc = lib.fc_sinkhorn(l, N, h, eps, gp, uu.ctypes.data, a.ctypes.data, itmax, tol, check_every,
                          ctypes.byref(iters), ctypes.byref(res))
     if rc:
         raise RuntimeError("fc_sinkhorn failed: %d" % rc)
-    return dict(log_phi=a, iters=iters.value, res=res.value, W=objective(a, h, eps))
+    return dict(log_phi=a, iters=iters.value, res=res.value, W=objective(a, h, eps, x))

@@ -94,6 +94,53 @@ def ricker_marginals(N: int, taus=(0.0, 0.75, 1.5), delta: float = 1e-3) -> np.n
     return np.stack(out)
 
 
+def graded_grid(N: int, seed: int = 0, spread: float = 0.8) -> np.ndarray:
+    """N increasing coordinates on [0, 1]: gaps drawn uniformly from
+    [1 - spread, 1 + spread] times the mean gap (seeded), scaled to end at 1."""
+    if N == 1:
+        return np.zeros(1)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 2**31 - 2])))
+    g = rng.uniform(1.0 - spread, 1.0 + spread, N - 1)
+    x = np.concatenate([[0.0], np.cumsum(g)])
+    return x / x[-1]
+
+
+def grid_marginals(x: np.ndarray, l: int, K: int = 2, master_seed: int = 0, instance: int = 0,
+                   floor: float = 1e-3) -> np.ndarray:
+    """Array [l, N] of Gaussian-mixture masses at the coordinates x (the uniform
+    recipe above with x in place of the uniform nodes)."""
+    N = x.shape[0]
+    out = []
+    for q in range(l):
+        rng = _rng(master_seed, instance, q)
+        mu = rng.uniform(0.2, 0.8, size=K)
+        sd = rng.uniform(0.05, 0.15, size=K)
+        dens = np.zeros(N)
+        for k in range(K):
+            dens += np.exp(-0.5 * ((x - mu[k]) / sd[k]) ** 2) / (sd[k] * np.sqrt(2.0 * np.pi))
+        p = dens / K + floor
+        out.append(p / p.sum())
+    return np.stack(out)
+
+
+def merge_supports(supports, weights):
+    """Marginals on their own supports -> (x, u) on one grid.
+
+    supports[q]: coordinates of marginal q (any order, distinct within q);
+    weights[q]: its non-negative masses.  x is the sorted union of all the
+    coordinates; u[q] holds marginal q's normalised masses at its own points and
+    zero elsewhere.
+    """
+    x = np.unique(np.concatenate([np.asarray(s, dtype=np.float64) for s in supports]))
+    u = np.zeros((len(supports), x.shape[0]))
+    for q, (s, w) in enumerate(zip(supports, weights)):
+        s = np.asarray(s, dtype=np.float64)
+        w = np.asarray(w, dtype=np.float64)
+        np.add.at(u[q], np.searchsorted(x, s), w)
+        u[q] /= u[q].sum()
+    return x, u
+
+
 # Named workloads.  Each entry: l, N, K, eps, floor, uniform_frac.
 WORKLOADS = {
     # plain method: l=3, N=64, 2 components, eps=0.1, fixed 500 sweeps
