@@ -60,6 +60,14 @@ typedef struct {
     double h;
     double eps;
     int32_t precision; /* MMOT_FP64 or MMOT_FP32 */
+    const double *x;   /* NULL: the uniform grid of step h.  Otherwise a non-uniform grid shared by
+                          the l marginals (Sec. 3 remarks that the method carries over to one): host
+                          [N] coordinates, finite and non-decreasing (MMOT_ERR_INVALID otherwise),
+                          copied by mmot_plan; h is then ignored.  The cost becomes
+                          sum_{p<q} |x[i_p] - x[i_q]| and gap k's factor exp(-(x[k+1] - x[k])
+                          m (l - m) / eps).  Marginals with different supports are given on the
+                          union of the supports with zero mass off their own.  Such problems run
+                          on the tiled kernels (any N) in the plan's precision. */
 } mmot_problem;
 
 /* Marginals passed to the solving calls (mmot_sinkhorn_iter, mmot_solve,
@@ -162,7 +170,8 @@ int mmot_solve(const mmot_plan_t *plan, const double *log_u, double *log_phi, mm
  * until the process ends; no call allocates.  Problems whose workspace would
  * exceed it are rejected with MMOT_ERR_INVALID before any device work.  Every
  * call on one GPU shares that GPU's workspace: calls that overlap on one GPU
- * (other streams or threads) race.  Runs the single-pass kernels (no tiles)
+ * (other streams or threads) race.  Uniform grids only (p->x must be NULL:
+ * MMOT_ERR_UNSUPPORTED otherwise).  Runs the single-pass kernels (no tiles)
  * in p->precision on hip_stream (NULL = default).  j, log_phi, log_J as in
  * mmot_marginal_product.
  */
@@ -178,7 +187,9 @@ int mmot_objective(const mmot_plan_t *plan, const double *log_phi, double *W);
  * err[j] = || phi_j * (K x_{q != j} phi_q) - u_j ||_1.  err: host [l], synchronises. */
 int mmot_marginal_errors(const mmot_plan_t *plan, const double *log_u, const double *log_phi, double *err);
 
-/* One instance of a batch or serving request.  log_u / log_phi: device [l][N]. */
+/* One instance of a batch.  log_u / log_phi: device [l][N].  x: NULL (uniform grid of
+ * step h) or device [N] coordinates of a non-uniform grid (as mmot_problem.x; checked on
+ * the device before any sweep). */
 typedef struct {
     int32_t l;
     int64_t N;
@@ -186,6 +197,7 @@ typedef struct {
     double eps;
     const double *log_u;
     double *log_phi;
+    const double *x;
 } mmot_instance;
 
 /*

@@ -86,14 +86,26 @@ struct mmot_plan {
     // tiled plans (long N): tile shape, host copies kept alive for async uploads
     bool tiled = false;
     int ntile = 1, B = 0;
+    double *dx = nullptr;  // non-uniform grid: device copy of the coordinates (tiled kernels)
     TileInst hTI;
     mutable Ptrs hP;
     mutable std::vector<char> jobs_host;
 };
 
-static int plan_flags(const mmot_opts &o)
+static int plan_flags(const mmot_opts &o, bool grid)
 {
-    return ((o.flags & MMOT_FLAG_TILES) ? F_TILES : 0) | ((o.flags & MMOT_FLAG_NO_GRAPH) ? F_NO_GRAPH : 0);
+    // a non-uniform grid runs on the tiled kernels only
+    return ((o.flags & MMOT_FLAG_TILES) || grid ? F_TILES : 0) | ((o.flags & MMOT_FLAG_NO_GRAPH) ? F_NO_GRAPH : 0);
+}
+
+// Host-side check of non-uniform grid coordinates: finite and non-decreasing.
+static int check_grid_host(const double *x, int64_t N)
+{
+    for (int64_t p = 0; p < N; ++p)
+        if (!std::isfinite(x[p]) || (p > 0 && !(x[p] >= x[p - 1])))
+            return fail(MMOT_ERR_INVALID, "grid coordinates must be finite and non-decreasing (index " +
+                                              std::to_string(p) + ")");
+    return MMOT_OK;
 }
 
 extern "C" {
@@ -105,8 +117,10 @@ int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_
     try {
         if (!p || !out) return fail(MMOT_ERR_INVALID, "problem or out is NULL");
         *out = nullptr;
-        int rc = check_shape(p->l, p->N, p->h, p->eps);
+        const bool grid = p->x != nullptr;
+        int rc = check_shape(p->l, p->N, grid ? 1.0 : p->h, p->eps);
         if (rc) return rc;
+        if (grid && (rc = check_grid_host(p->x, p->N))) return rc;
         if (p->precision != MMOT_FP64 && p->precision != MMOT_FP32)
             return fail(MMOT_ERR_INVALID, "precision must be MMOT_FP64 or MMOT_FP32");
         mmot_opts oo = {1e-8, 1000, 10, 0};
@@ -119,11 +133,20 @@ int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_
         pl->p = *p;
         pl->o = oo;
         pl->s = (hipStream_t)hip_stream;
-        const Inst I = make_inst(p->l, p->N, p->h, p->eps);
+        // on a non-uniform grid the gap lengths enter the factors and the objective's
+        // weights, so the objective takes no factor h (h = 1)
+        Inst I = make_inst(p->l, p->N, grid ? 1.0 : p->h, p->eps);
+        pl->tiled = tile_shape(p->l, p->N, plan_flags(oo, grid), &pl->ntile, &pl->B);
+        pl->scratch_size = scratch_bytes(p->l, p->N, p->precision, plan_flags(oo, grid));
+        hipError_t e = hipSuccess;
+        if (grid) {
+            e = hipMalloc((void **)&pl->dx, sizeof(double) * (size_t)p->N);
+            if (e == hipSuccess) e = hipMemcpy(pl->dx, p->x, sizeof(double) * (size_t)p->N, hipMemcpyHostToDevice);
+            I.x = pl->dx;
+        }
+        pl->p.x = nullptr;  // the caller's host array is not kept
         pl->hI = I;
-        pl->tiled = tile_shape(p->l, p->N, plan_flags(oo), &pl->ntile, &pl->B);
-        pl->scratch_size = scratch_bytes(p->l, p->N, p->precision, plan_flags(oo));
-        hipError_t e = hipMalloc((void **)&pl->dI, sizeof(Inst));
+        if (e == hipSuccess) e = hipMalloc((void **)&pl->dI, sizeof(Inst));
         if (e == hipSuccess) e = hipMalloc(&pl->scratch, std::max<size_t>(pl->scratch_size, 256));
         if (e == hipSuccess) e = hipMalloc((void **)&pl->dR, sizeof(Result));
         if (e == hipSuccess) e = hipMalloc((void **)&pl->dtmp, sizeof(double) * MAXL);
@@ -152,7 +175,8 @@ int mmot_plan_footprint(const mmot_plan_t *pl, size_t *device_bytes)
         if (!pl || !device_bytes) return fail(MMOT_ERR_INVALID, "NULL argument");
         *device_bytes = 2 * sizeof(Inst) + pl->scratch_size + 2 * sizeof(Result) + sizeof(double) * MAXL +
                         sizeof(Ptrs) + 3 * sizeof(int) + sizeof(Track) +
-                        2 * sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N;
+                        2 * sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N +
+                        (pl->dx ? sizeof(double) * (size_t)pl->p.N : 0);
         return MMOT_OK;
     } catch (...) {
         return guard_fail();
@@ -168,6 +192,7 @@ int mmot_plan_destroy(mmot_plan_t *pl)
         if (pl->scratch) (void)hipFree(pl->scratch);
         if (pl->dR) (void)hipFree(pl->dR);
         if (pl->dtmp) (void)hipFree(pl->dtmp);
+        if (pl->dx) (void)hipFree(pl->dx);
         delete pl;
         return MMOT_OK;
     } catch (...) {
@@ -245,7 +270,7 @@ int mmot_marginal_errors(const mmot_plan_t *pl, const double *log_u, const doubl
 
 static int plan_path(const mmot_plan_t *pl)
 {
-    return ((pl->o.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | plan_flags(pl->o);
+    return ((pl->o.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | plan_flags(pl->o, pl->dx != nullptr);
 }
 
 int mmot_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_phi, int64_t n_sweeps,
@@ -533,6 +558,8 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
             if (bad[i] & 1) return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": a marginal entry is NaN or negative");
             if (bad[i] & 2)
                 return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": a marginal's mass differs from 1 by more than 1e-12");
+            if (bad[i] & 4)
+                return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": grid coordinates must be finite and non-decreasing");
         }
     }
     size_t nother = robust[0].size() + robust[1].size();
@@ -781,19 +808,22 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
         size_t off = 0;
         std::vector<size_t> offs(count);
         for (int i = 0; i < count; ++i) {
-            rc = check_shape(inst[i].l, inst[i].N, inst[i].h, inst[i].eps);
+            const bool grid = inst[i].x != nullptr;
+            rc = check_shape(inst[i].l, inst[i].N, grid ? 1.0 : inst[i].h, inst[i].eps);
             if (rc) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
             if (!inst[i].log_u || !inst[i].log_phi) return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": NULL buffer");
-            hI[i] = make_inst(inst[i].l, inst[i].N, inst[i].h, inst[i].eps);
+            // non-uniform grid: tiled kernels, no factor h on the objective (as mmot_plan)
+            hI[i] = make_inst(inst[i].l, inst[i].N, grid ? 1.0 : inst[i].h, inst[i].eps);
+            hI[i].x = inst[i].x;
             offs[i] = off;
-            off += scratch_bytes(inst[i].l, inst[i].N, precision, (o->flags & MMOT_FLAG_TILES) ? F_TILES : 0);
+            off += scratch_bytes(inst[i].l, inst[i].N, precision, (o->flags & MMOT_FLAG_TILES) || grid ? F_TILES : 0);
         }
         std::lock_guard<std::mutex> lk(g_batch.mu);
         rc = g_batch.reserve((size_t)count, std::max<size_t>(off, 256));
         if (rc) return rc;
         for (int i = 0; i < count; ++i)
             hP[i] = {inst[i].log_u, inst[i].log_phi, nullptr, g_batch.scratch + offs[i], 0, 0,
-                     (o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0, 0};
+                     ((o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0) | (inst[i].x ? F_TILES : 0), 0};
         RunOpts ro = {o->tol, o->itr_max, o->check_every,
                       ((o->flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | ((o->flags & MMOT_FLAG_TILES) ? F_TILES : 0) |
                           ((o->flags & MMOT_FLAG_NO_GRAPH) ? F_NO_GRAPH : 0) |

@@ -59,6 +59,9 @@ struct Inst {
     Disc<double> d64;     // FP64 update and check scans
     Disc<double> dob;     // FP64 objective scans (value, cost-weighted value)
     Disc<double> dck;     // FP64 residual-check scans
+    const double *x;      // non-uniform grid: coordinates [N] on the device (team and tile walks
+                          // only); null for the uniform grid of step h
+    double ieps;          // 1 / eps
 };
 
 // Buffers of one solve (caller-owned except scratch).

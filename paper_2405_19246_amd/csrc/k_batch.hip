@@ -35,7 +35,14 @@ __global__ __launch_bounds__(256) void k_check_marginals(const Inst *I, const Pt
         c = (t - s) - y;
         s = t;
     }
-    if (b) atomicOr(&bad, 1);
+    // the coordinates of a non-uniform grid: finite and non-decreasing
+    const double *xs = I[i].x;
+    if (q == 0 && xs)
+        for (long p = threadIdx.x; p < N; p += blockDim.x) {
+            const double x = xs[p];
+            if (!(x - x == 0.0) || (p > 0 && !(x >= xs[p - 1]))) b |= 4;
+        }
+    if (b) atomicOr(&bad, b);
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {

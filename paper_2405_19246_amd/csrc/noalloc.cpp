@@ -50,6 +50,7 @@ extern "C" int mmot_marginal_product_noalloc(const mmot_problem *p, int32_t j, c
 {
     try {
         if (!p || !log_phi || !log_J) return fail(MMOT_ERR_INVALID, "NULL argument");
+        if (p->x) return fail(MMOT_ERR_UNSUPPORTED, "the workspace-free product takes uniform grids only");
         int rc = check_shape(p->l, p->N, p->h, p->eps);
         if (rc) return rc;
         if (p->precision != MMOT_FP64 && p->precision != MMOT_FP32)

@@ -59,6 +59,8 @@ Inst make_inst(int l, int64_t N, double h, double eps)
     I.l = l;
     I.h = h;
     I.hoe = h / eps;
+    I.ieps = 1.0 / eps;
+    I.x = nullptr;
     fill_disc<float>(I.d32, l, I.hoe, vsel(l, 0));
     fill_disc<double>(I.d64, l, I.hoe, vsel(l, 1));
     fill_disc<double>(I.dob, l, I.hoe, vsel(l, 2));
@@ -197,7 +199,7 @@ int tile_candidates(int l, int64_t N, int flags, int *cand)
         return 1;
     }
     int k = 0;
-    for (int c : {b / 2, b, 2 * b})
+    for (int c : {b / 4, b / 2, b, 2 * b})
         if (c >= 64 && c <= 8192) cand[k++] = c;
     return k;
 }
@@ -219,7 +221,7 @@ size_t tile_scratch_bytes(int l, int64_t N, int ntile, int B)
     // room for every length the autotuner may pick for this N
     (void)ntile;
     (void)B;
-    int cand[3];
+    int cand[4];
     const int k = tile_candidates(l, N, F_TILE_SMALL, cand);
     size_t best = 0;
     for (int i = 0; i < k; ++i) best = std::max(best, carve(l, (int)((N + cand[i] - 1) / cand[i]), cand[i]).total);

@@ -130,23 +130,9 @@ struct WConst {
     using M = typename ET<E>::MT;
     static constexpr int RB = WL<L, E>::RB;
     XG<M> g[RB + 1];
-    double pc[RB + 1];  // level (l - level): weight of a gap for the objective
+    double pc[RB + 1];  // level (l - level) (times the gap's length on a non-uniform grid):
+                        // weight of a gap for the objective
 };
-
-template <int L, typename E>
-__device__ __forceinline__ WConst<L, E> wconst(double hoe, int base, int sign)
-{
-    using M = typename ET<E>::MT;
-    WConst<L, E> c;
-#pragma unroll
-    for (int k = 0; k <= WL<L, E>::RB; ++k) {
-        const int lev = base + sign * k;
-        const bool ok = lev >= 0 && lev <= L;
-        c.g[k] = ok ? xg_from_log<M>(-(double)(lev * (L - lev)) * hoe) : XG<M>{M(0), M(0), XF_ZERO_E, 0};
-        c.pc[k] = ok ? (double)(lev * (L - lev)) : 0.0;
-    }
-    return c;
-}
 
 // a + b p for extended values, the result left unnormalized: the exponents are
 // aligned to the larger one and the mantissas meet in one FMA.  Within one
@@ -174,11 +160,16 @@ __device__ __forceinline__ void wstep(E (&A)[RG_], const XF<typename ET<E>::MT> 
     using T_ = ET<E>;
 #pragma unroll
     for (int i = 0; i < W::RG; ++i) A[i] = T_::disc(A[i], c.g[popc(i)], c.pc[popc(i)]);
-    // items across lanes
+    // items across lanes.  With teams of 16 lanes or more every moved value comes
+    // from a live lane of the team (or is the DPP's zero at a row edge), so every
+    // lane takes the MAC and a lane whose states do not hold the item multiplies
+    // by an exact zero (exponent XF_ZERO_E): its mantissa and exponent stay as
+    // they were.  Narrower teams share DPP rows with neighbours that may have
+    // left, and select instead.
 #pragma unroll
     for (int r = 0; r < W::LB; ++r) {
-        const XF<typename T_::MT> p = ph[r];
         const bool upd = BWD ? !((t >> r) & 1) : ((t >> r) & 1);
+        const XF<typename T_::MT> p = (W::TL >= 16) ? esel(upd, ph[r], xzero<typename T_::MT>()) : ph[r];
 #pragma unroll
         for (int i = 0; i < W::RG; ++i) {
             const E o = (r == 0)   ? lmove<0, BWD>(A[i])
@@ -188,7 +179,7 @@ __device__ __forceinline__ void wstep(E (&A)[RG_], const XF<typename ET<E>::MT> 
                         : (r == 4) ? lmove<4, BWD>(A[i])
                                    : lmove<5, BWD>(A[i]);
             const E nv = xmac_lazy(A[i], o, p);
-            A[i] = esel(upd, nv, A[i]);
+            A[i] = (W::TL >= 16) ? nv : esel(upd, nv, A[i]);
         }
     }
     // items across registers
@@ -232,17 +223,25 @@ struct WTeam {
     int t;                 // lane inside the team
     bool last;             // the team's last lane (holds team totals)
     XF<M> *ph;             // LDS [CK][n] scaling factors of the staged block
+    XG<M> *gt;             // LDS [CK + 1][l + 1] gap factors g(level) of the staged block (row s:
+                           // the gap before its position s); one row on the uniform grid
+    double *gd;            // LDS [CK + 1] those gaps' lengths (non-uniform grid)
     E *ck;                 // scratch: checkpoints [blocks][D]
 };
 
 // Stage phi of the summed marginals at the positions of one block into LDS:
 // slot s is position x0 + s (s < cnt), item r is marginal r < j ? r : r + 1.
+// With them the gap factors g_s(level) = exp(-d_s level (l - level) / eps) of the
+// gaps d_s between positions x0 + s - 1 and x0 + s, s = 0..cnt (a gap outside
+// [0, N) has length 0): on the uniform grid every gap is h and one row, from
+// h / eps, serves the whole block.
 template <int L, typename E>
-__device__ __forceinline__ void stage_phi(const WTeam<L, E> &tm, const double *__restrict__ a, long N, int j,
-                                          long x0, int cnt)
+__device__ __forceinline__ void stage_phi(const WTeam<L, E> &tm, const Inst *__restrict__ I,
+                                          const double *__restrict__ a, int j, long x0, int cnt)
 {
     using W = WL<L, E>;
     using M = typename ET<E>::MT;
+    const long N = I->N;
     team_sync();
     for (int k = tm.t; k < W::CK * W::n; k += W::TL) {
         const int s = k / W::n, r = k - s * W::n;
@@ -251,7 +250,44 @@ __device__ __forceinline__ void stage_phi(const WTeam<L, E> &tm, const double *_
         if (s < cnt) v = xfrom_log<M>(a[(long)q * N + x0 + s]);
         tm.ph[s * W::n + r] = v;
     }
+    const double *xs = I->x;
+    const int rows = xs ? cnt + 1 : 1;
+    for (int k = tm.t; k < rows * (L + 1); k += W::TL) {
+        const int s = k / (L + 1), lev = k - s * (L + 1);
+        double lg;
+        if (xs) {
+            const long p = x0 + s;
+            const double d = (p >= 1 && p < N) ? xs[p] - xs[p - 1] : 0.0;
+            if (lev == 0) tm.gd[s] = d;
+            lg = -(double)(lev * (L - lev)) * (d * I->ieps);
+        } else {
+            lg = -(double)(lev * (L - lev)) * I->hoe;
+        }
+        tm.gt[k] = xg_from_log<M>(lg);
+    }
     team_sync();
+}
+
+// Walk constants of one position from the staged gap factors: row of the gap
+// crossed, this lane's level base and direction (as wconst).  The objective's
+// cost weight of a gap is level (l - level) times its length on a non-uniform
+// grid, times 1 on the uniform grid (where h multiplies the total).
+template <int L, typename E>
+__device__ __forceinline__ WConst<L, E> wconst_row(const WTeam<L, E> &tm, bool grid, int row, int base, int sign)
+{
+    using M = typename ET<E>::MT;
+    WConst<L, E> c;
+    const XG<M> *g = tm.gt + (grid ? row : 0) * (L + 1);
+    const double d = grid ? tm.gd[row] : 1.0;
+#pragma unroll
+    for (int k = 0; k <= WL<L, E>::RB; ++k) {
+        const int lev = base + sign * k;
+        const bool ok = lev >= 0 && lev <= L;
+        const XG<M> v = g[ok ? lev : 0];
+        c.g[k] = {ok ? v.hi : M(0), ok ? v.lo : M(0), ok ? v.e : XF_ZERO_E, 0};
+        c.pc[k] = ok ? (double)(lev * (L - lev)) * d : 0.0;
+    }
+    return c;
 }
 
 // Accumulator of a pass's per-position results (the FP64 estimate, residual or
@@ -278,8 +314,7 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
     const long N = I->N;
     const int t = tm.t;
     const int pt = popc(t);
-    const WConst<L, E> cF = wconst<L, E>(I->hoe, pt, 1);
-    const WConst<L, E> cB = wconst<L, E>(I->hoe, n - pt, -1);
+    const bool grid = I->x != nullptr;
 
     WAcc acc = {0.0, xzero<double>()};
     const long len = p1 - p0;
@@ -299,8 +334,8 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
 #pragma unroll
         for (int i = 0; i < RG; ++i) tm.ck[b * D + i * W::TL + t] = A[i];
         if (b == nblk - 1) break;  // the last block's forward states are recomputed below
-        stage_phi<L, E>(tm, a, N, j, x0, cnt);
-        for (int s = 0; s < cnt; ++s) wstep<L, E, false>(A, tm.ph + s * n, cF, t);
+        stage_phi<L, E>(tm, I, a, j, x0, cnt);
+        for (int s = 0; s < cnt; ++s) wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt, 1), t);
     }
     team_sync();
 
@@ -314,14 +349,14 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
     for (long b = nblk - 1; b >= 0; --b) {
         const long x0 = p0 + b * CK;
         const int cnt = (int)min((long)CK, p1 - x0);
-        stage_phi<L, E>(tm, a, N, j, x0, cnt);
+        stage_phi<L, E>(tm, I, a, j, x0, cnt);
         // forward states of the block
         E F[CK][RG];
 #pragma unroll
         for (int i = 0; i < RG; ++i) A[i] = tm.ck[b * D + i * W::TL + t];
 #pragma unroll
         for (int s = 0; s < CK; ++s) {
-            if (s < cnt) wstep<L, E, false>(A, tm.ph + s * n, cF, t);
+            if (s < cnt) wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt, 1), t);
 #pragma unroll
             for (int i = 0; i < RG; ++i) F[s][i] = A[i];
         }
@@ -329,6 +364,8 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
         for (int s = CK - 1; s >= 0; --s) {
             if (s >= cnt) continue;
             const long y = x0 + s;
+            // the gap (y, y + 1): row s + 1
+            const WConst<L, E> cB = wconst_row<L, E>(tm, grid, s + 1, n - pt, -1);
             // J(y) = sum_S F_y(S) g(|R \ S|) B_{y+1}(R \ S)
             E part = T_::zero();
 #pragma unroll
@@ -395,7 +432,13 @@ struct WShared {
     static constexpr int B64 = WL<L, XF<double>>::CK * n * (int)sizeof(XF<double>);
     static constexpr int BOB = WL<L, DXF>::CK * n * (int)sizeof(XF<double>);
     static constexpr int M1 = B32 > B64 ? B32 : B64;
-    static constexpr int BYTES = M1 > BOB ? M1 : BOB;
+    static constexpr int PH = ((M1 > BOB ? M1 : BOB) + 15) / 16 * 16;
+    // gap-factor rows: as many as the longest block has positions, plus one
+    static constexpr int C1 = WL<L, XF<float>>::CK > WL<L, XF<double>>::CK ? WL<L, XF<float>>::CK
+                                                                           : WL<L, XF<double>>::CK;
+    static constexpr int ROWS = (C1 > WL<L, DXF>::CK ? C1 : WL<L, DXF>::CK) + 1;
+    static constexpr int GT = ROWS * (L + 1) * (int)sizeof(XG<double>);
+    static constexpr int BYTES = (PH + GT + ROWS * (int)sizeof(double) + 15) / 16 * 16;
     static constexpr int TPWMAX = WL<L, XF<float>>::TPW;  // TL does not depend on the element kind
 };
 
@@ -410,7 +453,10 @@ __device__ __forceinline__ WTeam<L, E> make_team(char *lds, void *scratch)
     WTeam<L, E> tm;
     tm.t = lane & (W::TL - 1);
     tm.last = tm.t == W::TL - 1;
-    tm.ph = reinterpret_cast<XF<typename ET<E>::MT> *>(lds + (lane / W::TL) * WShared<L>::BYTES);
+    char *base = lds + (lane / W::TL) * WShared<L>::BYTES;
+    tm.ph = reinterpret_cast<XF<typename ET<E>::MT> *>(base);
+    tm.gt = reinterpret_cast<XG<typename ET<E>::MT> *>(base + WShared<L>::PH);
+    tm.gd = reinterpret_cast<double *>(base + WShared<L>::PH + WShared<L>::GT);
     tm.ck = reinterpret_cast<E *>(scratch);
     return tm;
 }
@@ -579,26 +625,27 @@ __device__ void tile_agg_job(const WTeam<L, E> &tm, const Inst *__restrict__ I, 
     const long N = I->N;
     const long p0 = (long)t * T.B, p1 = min(N, p0 + T.B);
     const int pt = popc(tm.t);
+    const bool grid = I->x != nullptr;
     E A[RG];
     if (dir == 0) {
-        const WConst<L, E> c = wconst<L, E>(I->hoe, pt + m, 1);
 #pragma unroll
         for (int i = 0; i < RG; ++i) A[i] = esel(i * W::TL + tm.t == 0, T_::one(), T_::zero());
         for (long x0 = p0; x0 < p1; x0 += CK) {
             const int cnt = (int)min((long)CK, p1 - x0);
-            stage_phi<L, E>(tm, a, N, j, x0, cnt);
-            for (int s = 0; s < cnt; ++s) wstep<L, E, false>(A, tm.ph + s * n, c, tm.t);
+            stage_phi<L, E>(tm, I, a, j, x0, cnt);
+            for (int s = 0; s < cnt; ++s)
+                wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt + m, 1), tm.t);
         }
     } else {
-        const WConst<L, E> c = wconst<L, E>(I->hoe, m + n - pt, -1);
 #pragma unroll
         for (int i = 0; i < RG; ++i) A[i] = esel(i * W::TL + tm.t == D - 1, T_::one(), T_::zero());
         const long nb = (p1 - p0 + CK - 1) / CK;
         for (long b = nb - 1; b >= 0; --b) {
             const long x0 = p0 + b * CK;
             const int cnt = (int)min((long)CK, p1 - x0);
-            stage_phi<L, E>(tm, a, N, j, x0, cnt);
-            for (int s = cnt - 1; s >= 0; --s) wstep<L, E, true>(A, tm.ph + s * n, c, tm.t);
+            stage_phi<L, E>(tm, I, a, j, x0, cnt);
+            for (int s = cnt - 1; s >= 0; --s)
+                wstep<L, E, true>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s + 1, m + n - pt, -1), tm.t);
         }
     }
     E *q = reinterpret_cast<E *>(T.agg) + (((long)t * 2 + dir) * L + m) * D;
@@ -636,33 +683,36 @@ __device__ __forceinline__ DXF chain_mac(DXF acc, DXF a, DXF b)
     return {xmac_lazy(acc.v, a.v, b.v), xmac_lazy(xmac_lazy(acc.w, a.v, b.w), a.w, b.v)};
 }
 
-// The i-th subset of S in decreasing order (i = 0 is S itself): the bits of
-// 2^|S| - 1 - i dealt into the positions of S's members.
-__device__ __forceinline__ int nth_subset_desc(int S, int i)
-{
-    int x = (1 << popc(S)) - 1 - i, out = 0;
-    for (int b = 0, k = 0; b < 16; ++b)
-        if ((S >> b) & 1) out |= ((x >> k++) & 1) << b;
-    return out;
-}
-
 constexpr int CHAIN_THREADS = 512;
+constexpr int CHAIN_CHUNK = 16;  // subset terms per work item
 
-// Number of work items of a hop over the subsets of n items.
+// Number of work items of a hop over the subsets of n items: S with 2^|S|
+// subsets has ceil(2^|S| / CHAIN_CHUNK) of them.
 __host__ __device__ constexpr int chain_items(int n)
 {
     int tot = 0;
-    for (int S = 0; S < (1 << n); ++S) tot += ((1 << __builtin_popcount(S)) + 32 - 1) / 32;
+    for (int S = 0; S < (1 << n); ++S) tot += ((1 << __builtin_popcount(S)) + CHAIN_CHUNK - 1) / CHAIN_CHUNK;
     return tot;
 }
-constexpr int CHAIN_CHUNK = 32;  // subsets per work item
+
+// The hop's aggregates are staged in LDS when they fit beside the rest.
+template <int L, typename E>
+constexpr bool chain_stages()
+{
+    return sizeof(E) * (size_t)L * WL<L, E>::D + sizeof(E) * (size_t)(WL<L, E>::D + chain_items(L - 1)) +
+               sizeof(int) * (size_t)chain_items(L - 1) <=
+           (size_t)136 * 1024;
+}
 
 // Carries from tile to tile in one direction, one workgroup per (instance,
 // direction).  In subset space (forward: S as held; backward: the complement of
 // the index), c_next(S) = sum_{S' subset S} c(S') Q_{|S'|}(S \ S') with c(empty) = 1.
 // The 3^(l-1) terms of a hop are dealt to the threads as work items of at most
-// CHAIN_CHUNK subsets of one S; each item's partial sum goes to LDS and a second
-// phase adds the items of each S.
+// CHAIN_CHUNK subsets S' of one S (S' walked downwards from a stored start);
+// each item's partial sum goes to LDS and a second phase adds the items of each
+// S.  The tile's l 2^(l-1) aggregates are read into registers during the previous
+// hop and stored to LDS at the start of their own, so a hop waits on no global
+// load.
 template <int L, typename E>
 __global__ __launch_bounds__(CHAIN_THREADS) void k_tile_chain(const TileInst *TI, const TileTrack *Tr,
                                                               const int2 *jobs, int njobs, int state_need)
@@ -670,11 +720,15 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_tile_chain(const TileInst *TI
     using T_ = ET<E>;
     constexpr int D = WL<L, E>::D;
     constexpr int n = L - 1;
-    // work items: S with 2^|S| subsets has ceil(2^|S| / CHAIN_CHUNK) of them
     constexpr int MAXI = chain_items(n);
+    constexpr bool STAGE = chain_stages<L, E>();
+    constexpr int QN = L * D;
+    constexpr int PF = STAGE ? (QN + CHAIN_THREADS - 1) / CHAIN_THREADS : 1;
     __shared__ E c[D];
     __shared__ E part[MAXI];
+    __shared__ int item[MAXI];  // S | start S' << 10 | count << 20
     __shared__ int ioff[D + 1];
+    __shared__ E qs[STAGE ? QN : 1];
     const int2 jb = jobs[blockIdx.x];
     if (Tr && Tr[jb.x].state != state_need) return;
     const TileInst T = TI[jb.x];
@@ -685,35 +739,59 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_tile_chain(const TileInst *TI
         int o = 0;
         for (int S = 0; S < D; ++S) {
             ioff[S] = o;
-            o += ((1 << popc(S)) + CHAIN_CHUNK - 1) / CHAIN_CHUNK;
+            // subsets of S in decreasing order, CHAIN_CHUNK at a time
+            int Sp = S, left = 1 << popc(S);
+            while (left > 0) {
+                const int cnt = min(CHAIN_CHUNK, left);
+                item[o++] = S | (Sp << 10) | (cnt << 20);
+                for (int k = 0; k < cnt; ++k) Sp = (Sp - 1) & S;
+                left -= cnt;
+            }
         }
         ioff[D] = o;
     }
     for (int S = tid; S < D; S += blockDim.x) c[S] = esel(S == 0, T_::one(), T_::zero());
-    __syncthreads();
-    const int nitems = ioff[D];
     E *carry = reinterpret_cast<E *>(T.carry);
     const E *agg = reinterpret_cast<const E *>(T.agg);
+    auto hop_q = [&](int s) { return agg + ((long)(dir == 0 ? s : T.ntile - 1 - s) * 2 + dir) * QN; };
+    // prefetch registers: entry k of this thread is aggregate min(tid + k 512, QN - 1),
+    // moved as 32-bit words (a struct copy with padding would go through scratch)
+    constexpr int WD = (int)(sizeof(E) / 4);
+    int pre[PF][WD];
+    auto fetch = [&](const E *q) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int *src = reinterpret_cast<const int *>(q + min(tid + k * CHAIN_THREADS, QN - 1));
+#pragma unroll
+            for (int w = 0; w < WD; ++w) pre[k][w] = src[w];
+        }
+    };
+    if (STAGE && T.ntile > 1) fetch(hop_q(0));
+    __syncthreads();
     for (int s = 0; s < T.ntile; ++s) {
         const int t = dir == 0 ? s : T.ntile - 1 - s;
         for (int S = tid; S < D; S += blockDim.x) carry[((long)t * 2 + dir) * D + idx(S)] = c[S];
         if (s == T.ntile - 1) break;
-        const E *q = agg + ((long)t * 2 + dir) * L * D;
-        for (int it = tid; it < nitems; it += blockDim.x) {
-            // the item's state: the last S with ioff[S] <= it (binary search)
-            int lo = 0, hi = D - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (ioff[mid] <= it) lo = mid;
-                else hi = mid - 1;
-            }
-            const int S = lo;
-            const int k0 = (it - ioff[S]) * CHAIN_CHUNK;
-            const int cnt = min(CHAIN_CHUNK, (1 << popc(S)) - k0);
-            int Sp = nth_subset_desc(S, k0);
+        const E *q = hop_q(s);
+        if (STAGE) {
+#pragma unroll
+            for (int k = 0; k < PF; ++k)
+                if (tid + k * CHAIN_THREADS < QN) {
+                    int *dst = reinterpret_cast<int *>(qs + tid + k * CHAIN_THREADS);
+#pragma unroll
+                    for (int w = 0; w < WD; ++w) dst[w] = pre[k][w];
+                }
+            __syncthreads();
+            fetch(hop_q(min(s + 1, T.ntile - 2)));
+            q = qs;
+        }
+        for (int it = tid; it < ioff[D]; it += blockDim.x) {
+            const int w = item[it];
+            const int S = w & 1023, cnt = w >> 20;
+            int Sp = (w >> 10) & 1023;
             E acc = T_::zero();
             for (int k = 0; k < cnt; ++k) {
-                acc = chain_mac(acc, c[Sp], q[(long)popc(Sp) * D + idx(S ^ Sp)]);
+                acc = chain_mac(acc, c[Sp], q[popc(Sp) * D + idx(S ^ Sp)]);
                 Sp = (Sp - 1) & S;
             }
             part[it] = xnorm(acc);

@@ -28,7 +28,8 @@ _c_d, _c_i32, _c_i64, _c_p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ct
 
 
 class Problem(ctypes.Structure):
-    _fields_ = [("l", _c_i32), ("N", _c_i64), ("h", _c_d), ("eps", _c_d), ("precision", _c_i32)]
+    _fields_ = [("l", _c_i32), ("N", _c_i64), ("h", _c_d), ("eps", _c_d), ("precision", _c_i32),
+                ("x", ctypes.POINTER(_c_d))]
 
 
 class Opts(ctypes.Structure):
@@ -44,7 +45,8 @@ class Result(ctypes.Structure):
 
 
 class Instance(ctypes.Structure):
-    _fields_ = [("l", _c_i32), ("N", _c_i64), ("h", _c_d), ("eps", _c_d), ("log_u", _c_p), ("log_phi", _c_p)]
+    _fields_ = [("l", _c_i32), ("N", _c_i64), ("h", _c_d), ("eps", _c_d), ("log_u", _c_p), ("log_phi", _c_p),
+                ("x", _c_p)]
 
 
 class ServeCfg(ctypes.Structure):
@@ -160,15 +162,27 @@ def _dev_f64(t, shape, name):
     return t.data_ptr()
 
 
+def _host_grid(x, N):
+    """Host float64 copy of grid coordinates and a pointer to it (None: uniform grid)."""
+    if x is None:
+        return None, None
+    g = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if g.shape != (N,):
+        raise ValueError("x has shape %s, expected (%d,)" % (g.shape, N))
+    return g, g.ctypes.data_as(ctypes.POINTER(_c_d))
+
+
 class Plan:
-    """Execution plan for one problem shape (mmot_plan)."""
+    """Execution plan for one problem shape (mmot_plan).  x: optional host array of N
+    non-decreasing grid coordinates (non-uniform grid; h is then ignored)."""
 
     def __init__(self, l: int, N: int, h: float, eps: float, precision: int = FP64, tol: float = 1e-8,
                  itr_max: int = 1000, check_every: int = 10, warm_start: bool = False, stream=None,
-                 fast: bool = True, tiles: bool = False, graph: bool = True):
+                 fast: bool = True, tiles: bool = False, graph: bool = True, x=None):
         self.l, self.N, self.h, self.eps, self.precision = int(l), int(N), float(h), float(eps), int(precision)
         self.stream = stream
-        p = Problem(self.l, self.N, self.h, self.eps, self.precision)
+        gx, px = _host_grid(x, self.N)
+        p = Problem(self.l, self.N, self.h, self.eps, self.precision, px)
         o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast, tiles, graph))
         h_ = _c_p()
         _check(lib().mmot_plan(ctypes.byref(p), ctypes.byref(o), _c_p(_stream_handle(stream)), ctypes.byref(h_)))
@@ -263,7 +277,8 @@ def last_batch_timing() -> dict:
 def solve_batch(instances: Sequence[dict], precision: int = FP32, tol: float = 1e-6, itr_max: int = 100000,
                 check_every: int = 10, warm_start: bool = False, stream=None, fast: bool = True,
                 tiles: bool = False, graph: bool = True) -> list:
-    """mmot_solve_batch: instances are dicts with l, N, h, eps, log_u, log_phi (device tensors).
+    """mmot_solve_batch: instances are dicts with l, N, h, eps, log_u, log_phi (device tensors) and
+    optionally x (device tensor of N non-decreasing grid coordinates: a non-uniform grid).
 
     fast=False sets MMOT_FLAG_NO_FAST (every solve on the extended-range solver); tiles=True sets
     MMOT_FLAG_TILES (every instance cut into tiles that run on many teams of lanes)."""
@@ -272,7 +287,8 @@ def solve_batch(instances: Sequence[dict], precision: int = FP32, tol: float = 1
     for i, d in enumerate(instances):
         pu = _dev_f64(d["log_u"], (d["l"], d["N"]), "log_u")
         pa = _dev_f64(d["log_phi"], (d["l"], d["N"]), "log_phi")
-        arr[i] = Instance(int(d["l"]), int(d["N"]), float(d["h"]), float(d["eps"]), pu, pa)
+        px = _dev_f64(d["x"], (d["N"],), "x") if d.get("x") is not None else None
+        arr[i] = Instance(int(d["l"]), int(d["N"]), float(d["h"]), float(d["eps"]), pu, pa, px)
     o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast, tiles, graph))
     res = (Result * max(n, 1))()
     _check(lib().mmot_solve_batch(arr, n, int(precision), ctypes.byref(o), _c_p(_stream_handle(stream)), res),

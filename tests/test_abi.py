@@ -35,10 +35,10 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_layouts_match_header_sizes():
     mmot = _lib()
-    assert ctypes.sizeof(mmot.Problem) == 40
+    assert ctypes.sizeof(mmot.Problem) == 48
     assert ctypes.sizeof(mmot.Opts) == 24
     assert ctypes.sizeof(mmot.Result) == 40
-    assert ctypes.sizeof(mmot.Instance) == 48
+    assert ctypes.sizeof(mmot.Instance) == 56
     assert ctypes.sizeof(mmot.BatchTiming) == 48
 
 
@@ -99,3 +99,25 @@ def test_noalloc_product_checks_before_device_work():
     assert L.mmot_marginal_product_noalloc(ctypes.byref(p), 4, dummy, dummy, None) == -1
     assert L.mmot_marginal_product_noalloc(ctypes.byref(p), 0, None, dummy, None) == -1
     assert L.mmot_marginal_product_noalloc(None, 0, dummy, dummy, None) == -1
+
+
+def test_plan_rejects_a_bad_grid_before_device_work():
+    # non-uniform grid coordinates are checked on the host before any allocation
+    import numpy as np
+    mmot = _lib()
+    out = ctypes.c_void_p()
+    for bad in (np.array([0.0, 0.2, 0.1, 0.5]), np.array([0.0, np.nan, 0.3, 0.5]), np.array([0.0, 0.1, 0.2, np.inf])):
+        x = np.ascontiguousarray(bad)
+        p = mmot.Problem(3, 4, 0.0, 0.1, 0, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        assert mmot.lib().mmot_plan(ctypes.byref(p), None, None, ctypes.byref(out)) == -1
+        assert "grid" in mmot.last_error()
+        assert out.value is None
+
+
+def test_noalloc_product_rejects_a_grid():
+    import numpy as np
+    mmot = _lib()
+    x = np.linspace(0.0, 1.0, 10)
+    p = mmot.Problem(3, 10, 0.0, 0.1, 0, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    dummy = ctypes.c_void_p(16)
+    assert mmot.lib().mmot_marginal_product_noalloc(ctypes.byref(p), 0, dummy, dummy, None) == -5
