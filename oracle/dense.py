@@ -168,6 +168,48 @@ def sinkhorn(u: np.ndarray, h: float, eps: float, itmax: int, tol: float = 0.0,
     return dict(log_phi=a, W=W, iters=it, res=res, res_hist=hist)
 
 
+def sinkhorn_jacobi(u: np.ndarray, h: float, eps: float, itmax: int, tol: float = 0.0,
+                    check_every: int = 1, x=None) -> dict:
+    """All-marginals (Jacobi) variant of the iteration, damped by 1/l.
+
+    Not the paper's order (Sec. 4.2 updates one marginal at a time with the
+    newest potentials); an alternative that converges to the same plan.  Every
+    sweep forms all l products J_j from the potentials at the start of the sweep
+    and moves each a_j by 1/l of its own block update:
+        a_j <- a_j + (log u_j - a_j - log J_j) / l.
+    The new potentials are the mean of the l single-block updates, so by the
+    concavity of the dual the dual value never decreases.  Res sums the L1
+    errors of all l marginals (no marginal is exact after a Jacobi sweep).
+    """
+    l, N = u.shape
+    logK = log_kernel(l, N, h, eps, x)
+    with np.errstate(divide="ignore"):
+        log_u = np.log(u)
+    a = np.full((l, N), -np.log(N))
+    res = np.inf
+    it = 0
+    while it < itmax and res > tol:
+        it += 1
+        J = np.stack([marginal_product_log(logK, a, j) for j in range(l)])
+        with np.errstate(invalid="ignore"):
+            step = np.where(np.isneginf(log_u), -np.inf, log_u - a - J)
+        a = np.where(np.isneginf(step), -np.inf, a + step / l)
+        if it % check_every == 0 or it == itmax:
+            res = sum(float(np.sum(np.abs(np.exp(a[j] + marginal_product_log(logK, a, j)) - u[j]))) for j in range(l))
+    return dict(log_phi=a, W=objective(l, N, h, eps, a, x), iters=it, res=res)
+
+
+def dual_value(u: np.ndarray, logK: np.ndarray, log_phi: np.ndarray) -> float:
+    """sum_j <u_j, a_j> - sum K prod_q phi_q: the (eps-scaled) dual objective whose block
+    maximisers are the Sinkhorn updates (zero-mass entries contribute nothing)."""
+    l = logK.ndim
+    lin = 0.0
+    for j in range(l):
+        m = u[j] > 0
+        lin += float(np.sum(u[j][m] * log_phi[j][m]))
+    return lin - float(np.sum(np.exp(log_plan(logK, log_phi))))
+
+
 def sinkhorn_linear(u: np.ndarray, h: float, eps: float, itmax: int) -> dict:
     """Alg. 1 exactly as stated, in the linear domain (no stabilisation).
 

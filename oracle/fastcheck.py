@@ -107,3 +107,27 @@ def sinkhorn(u: np.ndarray, h: float, eps: float, itmax: int, tol: float = 0.0,
     if rc:
         raise RuntimeError("fc_sinkhorn failed: %d" % rc)
     return dict(log_phi=a, iters=iters.value, res=res.value, W=objective(a, h, eps, x))
+
+
+def sinkhorn_jacobi(u: np.ndarray, h: float, eps: float, itmax: int, tol: float = 0.0,
+                    check_every: int = 1, log_phi0: np.ndarray | None = None, x=None) -> dict:
+    """The damped all-marginals (Jacobi) iteration of oracle/dense.py (sinkhorn_jacobi)
+    with this checker's products: every sweep forms all l products from the
+    potentials at its start, then a_j <- a_j + (log u_j - a_j - log J_j) / l.
+    Res sums the L1 errors of all l marginals."""
+    uu = _c(u)
+    l, N = uu.shape
+    with np.errstate(divide="ignore"):
+        log_u = np.log(uu)
+    a = np.full((l, N), -np.log(N)) if log_phi0 is None else _c(log_phi0).copy()
+    res = np.inf
+    it = 0
+    while it < itmax and res > tol:
+        it += 1
+        J = np.stack([marginal_product_log(a, j, h, eps, x) for j in range(l)])
+        with np.errstate(invalid="ignore"):
+            step = np.where(np.isneginf(log_u), -np.inf, log_u - a - J)
+        a = np.where(np.isneginf(step), -np.inf, a + step / l)
+        if it % check_every == 0 or it == itmax:
+            res = float(marginal_errors(uu, a, h, eps, x).sum())
+    return dict(log_phi=a, iters=it, res=res, W=objective(a, h, eps, x))

@@ -185,3 +185,41 @@ def test_linear_domain_breaks_where_log_domain_does_not():
     assert lin["failed_at"] is not None
     r = dense.sinkhorn(u, h, 1e-3, itmax=lin["failed_at"] + 5, check_every=1000)
     assert np.all(np.isfinite(r["log_phi"])) and np.isfinite(r["res"])
+
+
+def test_jacobi_ascends_the_dual_and_reaches_the_gauss_seidel_plan():
+    # the damped all-marginals sweep is the mean of the l block updates, so the
+    # concave dual never decreases; its limit is the unique entropic plan
+    l, N, eps = 3, 7, 0.2
+    u = inputs.marginals(l, N, K=2, master_seed=3, instance=1)
+    h = inputs.grid_step(N)
+    logK = dense.log_kernel(l, N, h, eps)
+    vals = []
+    for its in range(1, 30):
+        r = dense.sinkhorn_jacobi(u, h, eps, itmax=its)
+        vals.append(dense.dual_value(u, logK, r["log_phi"]))
+    assert all(b >= a - 1e-15 for a, b in zip(vals, vals[1:]))
+    gs = dense.sinkhorn(u, h, eps, itmax=5000, tol=1e-14)
+    jc = dense.sinkhorn_jacobi(u, h, eps, itmax=20000, tol=1e-13)
+    assert jc["res"] <= 1e-13
+    Pg = np.exp(dense.log_plan(logK, gs["log_phi"]))
+    Pj = np.exp(dense.log_plan(logK, jc["log_phi"]))
+    assert np.abs(Pg - Pj).sum() < 1e-12
+    assert abs(gs["W"] - jc["W"]) < 1e-12
+
+
+def test_undamped_jacobi_is_not_a_fixed_point_iteration_that_settles():
+    # without the 1/l damping the all-marginals update overshoots: at l = 3 the
+    # plan's mass is multiplied by the product of the three corrections, so the
+    # iterates cycle instead of settling (why the variant takes the mean)
+    l, N, eps = 3, 6, 0.2
+    u = inputs.marginals(l, N, K=2, master_seed=4, instance=0)
+    h = inputs.grid_step(N)
+    logK = dense.log_kernel(l, N, h, eps)
+    a = np.full((l, N), -np.log(N))
+    hist = []
+    for _ in range(60):
+        J = np.stack([dense.marginal_product_log(logK, a, j) for j in range(l)])
+        a = np.log(u) - J
+        hist.append(dense.residual(logK, a, u))
+    assert min(hist[-10:]) > 1e-3

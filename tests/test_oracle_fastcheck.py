@@ -74,3 +74,18 @@ def test_sinkhorn_matches_dense_wide(l, N, eps, its):
     err_d = np.abs(dense.plan_marginals(logK, rd["log_phi"]) - u).sum(axis=1)
     err = fastcheck.marginal_errors(u, rf["log_phi"], h, eps)
     np.testing.assert_allclose(err, err_d, rtol=1e-8, atol=1e-15)
+
+
+@pytest.mark.parametrize("l,N,its", [(3, 8, 12), (5, 5, 7)])
+def test_jacobi_matches_dense(l, N, its):
+    u = inputs.marginals(l, N, K=2, master_seed=l, instance=N)
+    u[1, 2] = 0.0
+    u /= u.sum(axis=1, keepdims=True)
+    h, eps = inputs.grid_step(N), 0.1
+    rd = dense.sinkhorn_jacobi(u, h, eps, itmax=its)
+    rf = fastcheck.sinkhorn_jacobi(u, h, eps, itmax=its, check_every=its)
+    fin = np.isfinite(rd["log_phi"])
+    assert np.array_equal(fin, np.isfinite(rf["log_phi"]))
+    np.testing.assert_allclose(rf["log_phi"][fin], rd["log_phi"][fin], rtol=1e-12, atol=1e-12)
+    assert abs(rf["W"] - rd["W"]) <= 1e-12 * abs(rd["W"])
+    assert abs(rf["res"] - rd["res"]) <= 1e-10 * rd["res"]
