@@ -94,7 +94,16 @@ typedef struct {
  * 512 instances off the register-resident path, every such instance from
  * N = 256 up; not with MMOT_FLAG_NO_FAST); MMOT_FLAG_NO_GRAPH launches
  * the tiled sweeps one by one instead of replaying a captured HIP graph of a
- * block of sweeps (same iterates, bit for bit). */
+ * block of sweeps (same iterates, bit for bit).
+ * MMOT_FLAG_JACOBI (mmot_plan only: honoured by mmot_solve and
+ * mmot_sinkhorn_iter; mmot_solve_batch rejects it): the all-marginals variant
+ * instead of the paper's Gauss-Seidel order (Sec. 4.2).  Every sweep forms the
+ * l products from the potentials at the start of the sweep, then moves each
+ * a_j by 1/l of its own update, a_j <- a_j + (log u_j - a_j - log J_j) / l: the
+ * mean of the l block updates, so the dual never decreases and the iterates
+ * reach the same (unique) plan.  Its residual sums the errors of all l
+ * marginals and is checked every check_every sweeps (every 10 if 0) and after
+ * the last; no estimate. */
 typedef struct {
     double tol;
     int64_t itr_max;
@@ -106,6 +115,7 @@ typedef struct {
 #define MMOT_FLAG_NO_FAST 2
 #define MMOT_FLAG_TILES 4
 #define MMOT_FLAG_NO_GRAPH 8
+#define MMOT_FLAG_JACOBI 16
 
 /* Per-solve outcome. */
 typedef struct {

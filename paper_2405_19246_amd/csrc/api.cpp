@@ -87,6 +87,7 @@ struct mmot_plan {
     bool tiled = false;
     int ntile = 1, B = 0;
     double *dx = nullptr;  // non-uniform grid: device copy of the coordinates (tiled kernels)
+    double *djac = nullptr;  // MMOT_FLAG_JACOBI: [l][N] products of one all-marginals sweep
     TileInst hTI;
     mutable Ptrs hP;
     mutable std::vector<char> jobs_host;
@@ -147,6 +148,8 @@ int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_
         pl->p.x = nullptr;  // the caller's host array is not kept
         pl->hI = I;
         if (e == hipSuccess) e = hipMalloc((void **)&pl->dI, sizeof(Inst));
+        if (e == hipSuccess && (oo.flags & MMOT_FLAG_JACOBI))
+            e = hipMalloc((void **)&pl->djac, sizeof(double) * (size_t)p->l * (size_t)p->N);
         if (e == hipSuccess) e = hipMalloc(&pl->scratch, std::max<size_t>(pl->scratch_size, 256));
         if (e == hipSuccess) e = hipMalloc((void **)&pl->dR, sizeof(Result));
         if (e == hipSuccess) e = hipMalloc((void **)&pl->dtmp, sizeof(double) * MAXL);
@@ -176,7 +179,8 @@ int mmot_plan_footprint(const mmot_plan_t *pl, size_t *device_bytes)
         *device_bytes = 2 * sizeof(Inst) + pl->scratch_size + 2 * sizeof(Result) + sizeof(double) * MAXL +
                         sizeof(Ptrs) + 3 * sizeof(int) + sizeof(Track) +
                         2 * sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N +
-                        (pl->dx ? sizeof(double) * (size_t)pl->p.N : 0);
+                        (pl->dx ? sizeof(double) * (size_t)pl->p.N : 0) +
+                        (pl->djac ? sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N : 0);
         return MMOT_OK;
     } catch (...) {
         return guard_fail();
@@ -193,6 +197,7 @@ int mmot_plan_destroy(mmot_plan_t *pl)
         if (pl->dR) (void)hipFree(pl->dR);
         if (pl->dtmp) (void)hipFree(pl->dtmp);
         if (pl->dx) (void)hipFree(pl->dx);
+        if (pl->djac) (void)hipFree(pl->djac);
         delete pl;
         return MMOT_OK;
     } catch (...) {
@@ -273,12 +278,82 @@ static int plan_path(const mmot_plan_t *pl)
     return ((pl->o.flags & MMOT_FLAG_NO_FAST) ? F_NO_FAST : 0) | plan_flags(pl->o, pl->dx != nullptr);
 }
 
+// The marginals of one plan call must be probability vectors (checked on the device).
+static int plan_validate(const mmot_plan_t *pl, const double *log_u, const double *log_phi)
+{
+    Ptrs P = {log_u, const_cast<double *>(log_phi), nullptr, pl->scratch, 0, 0, 0, 0};
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(pl->bb.dI, &pl->hI, sizeof(Inst), hipMemcpyHostToDevice, pl->s));
+    HIPCHK(hipMemcpyAsync(pl->bb.dP, &P, sizeof(Ptrs), hipMemcpyHostToDevice, pl->s));
+    HIPCHK(launch_check_marginals(pl->bb.dI, pl->bb.dP, 1, pl->bb.dflags, pl->s));
+    HIPCHK(hipMemcpyAsync(&bad, pl->bb.dflags, sizeof(int), hipMemcpyDeviceToHost, pl->s));
+    HIPCHK(hipStreamSynchronize(pl->s));
+    if (bad & 1) return fail(MMOT_ERR_INVALID, "a marginal entry is NaN or negative");
+    if (bad & 2) return fail(MMOT_ERR_INVALID, "a marginal's mass differs from 1 by more than 1e-12");
+    if (bad & 4) return fail(MMOT_ERR_INVALID, "grid coordinates must be finite and non-decreasing");
+    return MMOT_OK;
+}
+
+// MMOT_FLAG_JACOBI: up to max_sweeps all-marginals sweeps (l products from the
+// sweep's starting potentials into djac, then the damped update of every row),
+// the FP64 residual over all l marginals every check_every sweeps and after the
+// last, stopping once it is <= tol (tol < 0: never early).  Potentials start at
+// phi = 1/N unless warm.
+static int jacobi_run(const mmot_plan_t *pl, const double *log_u, double *log_phi, int64_t max_sweeps, double tol,
+                      int check_every, bool warm, bool want_res, int64_t *iters, double *res)
+{
+    const int l = pl->p.l;
+    const int64_t N = pl->p.N;
+    int rc = plan_validate(pl, log_u, log_phi);
+    if (rc) return rc;
+    if (!warm) HIPCHK(launch_fill(log_phi, (long)l * N, -std::log((double)N), pl->s));
+    const int every = check_every > 0 ? check_every : 10;
+    double r = INFINITY;
+    int64_t it = 0;
+    while (it < max_sweeps) {
+        ++it;
+        for (int j = 0; j < l; ++j) {
+            double *out = pl->djac + (size_t)j * (size_t)N;
+            if (pl->tiled) {
+                rc = plan_tile_pass(pl, P_PRODUCT, j, nullptr, log_phi, out);
+                if (rc) return rc;
+            } else {
+                Ptrs P = {nullptr, log_phi, out, pl->scratch, 0, 0, 0, 0};
+                HIPCHK(launch_pass(l, pl->p.precision, P_PRODUCT, pl->dI, P, j, nullptr, pl->s));
+            }
+        }
+        HIPCHK(launch_jacobi_update(log_phi, log_u, pl->djac, (long)l * N, l, pl->s));
+        if (want_res && (it % every == 0 || it == max_sweeps)) {
+            double err[MAXL];
+            rc = mmot_marginal_errors(pl, log_u, log_phi, err);
+            if (rc) return rc;
+            r = 0.0;
+            for (int j = 0; j < l; ++j) r += err[j];
+            if (!std::isfinite(r)) return fail(MMOT_ERR_NUMERIC, "non-finite residual");
+            if (tol >= 0.0 && r <= tol) break;
+        }
+    }
+    *iters = it;
+    *res = r;
+    return MMOT_OK;
+}
+
 int mmot_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_phi, int64_t n_sweeps,
                        double *marg_err)
 {
     try {
         if (!pl || !log_u || !log_phi) return fail(MMOT_ERR_INVALID, "NULL argument");
         if (n_sweeps < 0) return fail(MMOT_ERR_INVALID, "n_sweeps must be >= 0");
+        if (pl->djac && n_sweeps > 0) {
+            int64_t it = 0;
+            double r = 0.0;
+            // only the sweep count's last residual is computed (check_every = n_sweeps)
+            const int rc = jacobi_run(pl, log_u, log_phi, n_sweeps, -1.0, (int)std::min<int64_t>(n_sweeps, INT32_MAX),
+                                      true, marg_err != nullptr, &it, &r);
+            if (rc) return rc;
+            if (marg_err) *marg_err = r;
+            return MMOT_OK;
+        }
         if (n_sweeps > 0) {
             RunOpts o = {-1.0, n_sweeps, 0, F_WARM | F_NO_OBJ | F_VALIDATE | (marg_err ? 0 : F_NO_CHECK) | plan_path(pl)};
             Ptrs P = {log_u, log_phi, nullptr, pl->scratch, 0, 0, F_WARM, 0};
@@ -306,6 +381,26 @@ int mmot_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_p
 int mmot_solve(const mmot_plan_t *pl, const double *log_u, double *log_phi, mmot_result *res)
 {
     try {
+        if (pl && pl->djac && log_u && log_phi && res) {
+            const bool warm = (pl->o.flags & MMOT_FLAG_WARM_START) != 0;
+            int64_t it = 0;
+            double r = INFINITY;
+            int rc = jacobi_run(pl, log_u, log_phi, pl->o.itr_max, pl->o.tol, pl->o.check_every, warm, true, &it, &r);
+            if (rc) return rc;
+            double W = 0.0;
+            rc = mmot_objective(pl, log_phi, &W);
+            if (rc) return rc;
+            res->W = W;
+            res->marg_err = r;
+            res->iters = it;
+            res->l = pl->p.l;
+            res->N = pl->p.N;
+            const bool conv = pl->o.tol < 0.0 || r <= pl->o.tol;
+            res->status = !std::isfinite(W) ? MMOT_ERR_NUMERIC : conv ? MMOT_OK : MMOT_NOT_CONVERGED;
+            if (res->status == MMOT_ERR_NUMERIC) return fail(MMOT_ERR_NUMERIC, "non-finite objective");
+            if (res->status == MMOT_NOT_CONVERGED) g_err = "itr_max reached before tol";
+            return res->status;
+        }
         if (!pl || !log_u || !log_phi || !res) return fail(MMOT_ERR_INVALID, "NULL argument");
         const int warm = (pl->o.flags & MMOT_FLAG_WARM_START) ? F_WARM : 0;
         RunOpts o = {pl->o.tol, pl->o.itr_max, pl->o.check_every, plan_path(pl) | F_VALIDATE};
@@ -802,6 +897,7 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
         if (precision != MMOT_FP64 && precision != MMOT_FP32) return fail(MMOT_ERR_INVALID, "bad precision");
         int rc = check_opts(o);
         if (rc) return rc;
+        if (o->flags & MMOT_FLAG_JACOBI) return fail(MMOT_ERR_UNSUPPORTED, "MMOT_FLAG_JACOBI is a plan option");
         if (count == 0) return MMOT_OK;
         std::vector<Inst> hI(count);
         std::vector<Ptrs> hP(count);

@@ -56,6 +56,36 @@ __global__ __launch_bounds__(256) void k_check_marginals(const Inst *I, const Pt
     }
 }
 
+// All-marginals (Jacobi) sweep, second half: with log J_j of every marginal from
+// the potentials at the start of the sweep, a_j <- a_j + (log u_j - a_j - log J_j) / l
+// (zero mass keeps a_j = -inf).  n = l N entries, row-major [l][N] like a.
+__global__ void k_jacobi_update(double *a, const double *log_u, const double *logJ, long n, double inv_l)
+{
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) {
+        const double lu = log_u[p];
+        a[p] = (lu == -INFINITY) ? -INFINITY : a[p] + (lu - a[p] - logJ[p]) * inv_l;
+    }
+}
+
+__global__ void k_fill_f64(double *a, long n, double v)
+{
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) a[p] = v;
+}
+
+hipError_t launch_jacobi_update(double *a, const double *log_u, const double *logJ, long n, int l, hipStream_t s)
+{
+    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_jacobi_update, dim3(blocks), dim3(256), 0, s, a, log_u, logJ, n, 1.0 / (double)l);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *a, long n, double v, hipStream_t s)
+{
+    const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(256), 0, s, a, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_check_marginals(const Inst *dI, const Ptrs *dP, int count, int *dflags, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;

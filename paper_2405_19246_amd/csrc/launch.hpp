@@ -73,6 +73,10 @@ hipError_t launch_tile_ctrl(int l, int which, const Ptrs *dP, const TileInst *dT
 // instance i is NaN or +inf, |= 2 if a row's mass differs from 1 by more than
 // 1e-12 (FP64).  flags must be zero on entry.
 hipError_t launch_check_marginals(const Inst *dI, const Ptrs *dP, int count, int *dflags, hipStream_t s);
+// All-marginals sweep update from the l products of the sweep's starting potentials,
+// and a constant fill (potentials phi = 1/N).
+hipError_t launch_jacobi_update(double *a, const double *log_u, const double *logJ, long n, int l, hipStream_t s);
+hipError_t launch_fill(double *a, long n, double v, hipStream_t s);
 
 // phi = 1/N for the listed instances that do not start warm.
 hipError_t launch_tile_init(const Inst *dI, const Ptrs *dP, const int *dlist, int count, const RunOpts &o,

@@ -289,6 +289,8 @@ int mmot_serve_start(const mmot_serve_cfg *cfg, mmot_server_t **out)
         if (cfg->precision != MMOT_FP64 && cfg->precision != MMOT_FP32) return fail(MMOT_ERR_INVALID, "bad precision");
         int rc = check_opts(&cfg->opts);
         if (rc) return rc;
+        if (cfg->opts.flags & MMOT_FLAG_JACOBI)
+            return fail(MMOT_ERR_UNSUPPORTED, "MMOT_FLAG_JACOBI is a plan option");
         if (cfg->max_slots < 1) return fail(MMOT_ERR_INVALID, "max_slots must be >= 1");
         if (cfg->block_sweeps < 1) return fail(MMOT_ERR_INVALID, "block_sweeps must be >= 1");
         if (cfg->hbm_budget_bytes < 4096) return fail(MMOT_ERR_INVALID, "hbm_budget_bytes too small");

@@ -22,6 +22,7 @@ FLAG_WARM_START = 1
 FLAG_NO_FAST = 2
 FLAG_TILES = 4
 FLAG_NO_GRAPH = 8
+FLAG_JACOBI = 16
 MAX_L = 10
 
 _c_d, _c_i32, _c_i64, _c_p = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
@@ -146,9 +147,9 @@ def _stream_handle(stream) -> int:
     return int(s.cuda_stream)
 
 
-def _flags(warm_start: bool, fast: bool, tiles: bool = False, graph: bool = True) -> int:
+def _flags(warm_start: bool, fast: bool, tiles: bool = False, graph: bool = True, jacobi: bool = False) -> int:
     return ((FLAG_WARM_START if warm_start else 0) | (0 if fast else FLAG_NO_FAST) | (FLAG_TILES if tiles else 0) |
-            (0 if graph else FLAG_NO_GRAPH))
+            (0 if graph else FLAG_NO_GRAPH) | (FLAG_JACOBI if jacobi else 0))
 
 
 def _dev_f64(t, shape, name):
@@ -174,16 +175,17 @@ def _host_grid(x, N):
 
 class Plan:
     """Execution plan for one problem shape (mmot_plan).  x: optional host array of N
-    non-decreasing grid coordinates (non-uniform grid; h is then ignored)."""
+    non-decreasing grid coordinates (non-uniform grid; h is then ignored).  jacobi: the
+    damped all-marginals sweep (MMOT_FLAG_JACOBI) in solve and sinkhorn_iter."""
 
     def __init__(self, l: int, N: int, h: float, eps: float, precision: int = FP64, tol: float = 1e-8,
                  itr_max: int = 1000, check_every: int = 10, warm_start: bool = False, stream=None,
-                 fast: bool = True, tiles: bool = False, graph: bool = True, x=None):
+                 fast: bool = True, tiles: bool = False, graph: bool = True, x=None, jacobi: bool = False):
         self.l, self.N, self.h, self.eps, self.precision = int(l), int(N), float(h), float(eps), int(precision)
         self.stream = stream
         gx, px = _host_grid(x, self.N)
         p = Problem(self.l, self.N, self.h, self.eps, self.precision, px)
-        o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast, tiles, graph))
+        o = Opts(float(tol), int(itr_max), int(check_every), _flags(warm_start, fast, tiles, graph, jacobi))
         h_ = _c_p()
         _check(lib().mmot_plan(ctypes.byref(p), ctypes.byref(o), _c_p(_stream_handle(stream)), ctypes.byref(h_)))
         self._h = h_

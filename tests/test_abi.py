@@ -121,3 +121,14 @@ def test_noalloc_product_rejects_a_grid():
     p = mmot.Problem(3, 10, 0.0, 0.1, 0, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     dummy = ctypes.c_void_p(16)
     assert mmot.lib().mmot_marginal_product_noalloc(ctypes.byref(p), 0, dummy, dummy, None) == -5
+
+
+def test_jacobi_flag_is_a_plan_option():
+    mmot = _lib()
+    arr = (mmot.Instance * 1)()
+    dummy = ctypes.c_void_p(16)
+    arr[0] = mmot.Instance(3, 10, 0.1, 0.1, dummy, dummy, None)
+    o = mmot.Opts(1e-6, 10, 10, mmot.FLAG_JACOBI)
+    res = (mmot.Result * 1)()
+    assert mmot.lib().mmot_solve_batch(arr, 1, 1, ctypes.byref(o), None, res) == -5
+    assert "JACOBI" in mmot.last_error()
