@@ -197,6 +197,47 @@ int mmot_objective(const mmot_plan_t *plan, const double *log_phi, double *W);
  * err[j] = || phi_j * (K x_{q != j} phi_q) - u_j ||_1.  err: host [l], synchronises. */
 int mmot_marginal_errors(const mmot_plan_t *plan, const double *log_u, const double *log_phi, double *err);
 
+/*
+ * Three marginals on an N x M grid with separable L1 cost (Sec. 4.1):
+ *   c = h1 (|i1 - j1| + |i1 - k1| + |j1 - k1|) + h2 (|i2 - j2| + |i2 - k2| + |j2 - k2|).
+ * A marginal (and its potentials, products, errors) is a device array [M][N] of
+ * FP64: entry (i1, i2) at i2 N + i1, the paper's column-major flattening; the
+ * three of a solve are stacked as [3][M][N].  Everything runs in FP64: each
+ * product is a scan along the second axis whose steps are 6 M independent 1-D
+ * three-marginal products of length N (Sec. 4.1 recurrences, O(N M) work).
+ * Plans take MMOT_FLAG_WARM_START only (MMOT_ERR_UNSUPPORTED otherwise); the
+ * stopping rule checks the FP64 residual every check_every sweeps (every 10 if
+ * 0) and after the last.
+ */
+typedef struct {
+    int64_t N;   /* points along the first axis (spacing h1) */
+    int64_t M;   /* points along the second axis (spacing h2) */
+    double h1;
+    double h2;
+    double eps;
+} mmot_problem_2d;
+
+typedef struct mmot_plan_2d mmot_plan_2d_t;
+
+int mmot_plan_2d(const mmot_problem_2d *p, const mmot_opts *o, void *hip_stream, mmot_plan_2d_t **out);
+int mmot_plan_2d_destroy(mmot_plan_2d_t *plan);
+
+/* log_J[y][x] = log (K x_{q != j} phi_q)(x, y), j in 0..2 (Sec. 4.1 Eq. for J_{k1 k2}).
+ * log_phi: device [3][M][N], row j ignored; log_J: device [M][N]. */
+int mmot_marginal_product_2d(const mmot_plan_2d_t *plan, int32_t j, const double *log_phi, double *log_J);
+
+/* Gauss-Seidel sweeps (Sec. 4.1 update formulas) from phi = 1/(N M) unless warm,
+ * until Res = err_0 + err_1 <= tol or itr_max, then W_eps = <C, T> in FP64.
+ * log_u: device [3][M][N], probability vectors (MMOT_ERR_INVALID otherwise);
+ * log_phi: device [3][M][N] out.  res: host; res->N is N M. */
+int mmot_solve_2d(const mmot_plan_2d_t *plan, const double *log_u, double *log_phi, mmot_result *res);
+
+/* W_eps = <C, T> of the plan with potentials log_phi (Sec. 4.1 Eq. 2-D distance).  W: host. */
+int mmot_objective_2d(const mmot_plan_2d_t *plan, const double *log_phi, double *W);
+
+/* FP64 L1 errors of the three marginals of the plan.  err: host [3]. */
+int mmot_marginal_errors_2d(const mmot_plan_2d_t *plan, const double *log_u, const double *log_phi, double *err);
+
 /* One instance of a batch.  log_u / log_phi: device [l][N].  x: NULL (uniform grid of
  * step h) or device [N] coordinates of a non-uniform grid (as mmot_problem.x; checked on
  * the device before any sweep). */

@@ -37,6 +37,14 @@ def _lse(x):
     return m + np.log(np.sum(np.exp(x - m)))
 
 
+def _lse0(T):
+    """log sum exp over axis 0 of a 2-D array, column by column, with a max shift."""
+    m = np.max(T, axis=0)
+    ms = np.where(np.isfinite(m), m, 0.0)
+    with np.errstate(divide="ignore"):
+        return np.log(np.sum(np.exp(T - ms), axis=0)) + ms
+
+
 def _e3(i, j, k):
     return abs(i - j) + abs(i - k) + abs(j - k)
 
@@ -124,8 +132,8 @@ def product(a: np.ndarray, j: int, h1: float, h2: float, eps: float) -> np.ndarr
         F[i2, j2] = ftvp(a[p, i2], a[q, j2], h1, eps)
     out = np.empty((M, N))
     for k2 in range(M):
-        terms = [lam2 * _e3(i2, j2, k2) + F[i2, j2] for i2, j2 in itertools.product(range(M), repeat=2)]
-        out[k2] = [_lse([t[i1] for t in terms]) for i1 in range(N)]
+        terms = np.stack([lam2 * _e3(i2, j2, k2) + F[i2, j2] for i2, j2 in itertools.product(range(M), repeat=2)])
+        out[k2] = _lse0(terms)
     return out
 
 

@@ -48,6 +48,8 @@ def _units():
     units.append((os.path.join(HERE, "serve.cpp"), "serve.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "tile.cpp"), "tile.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "noalloc.cpp"), "noalloc.o", ["-x", "hip"]))
+    units.append((os.path.join(HERE, "twod.cpp"), "twod.o", ["-x", "hip"]))
+    units.append((os.path.join(HERE, "k_2d.hip"), "k_2d.o", []))
     units.append((os.path.join(HERE, "tables.cpp"), "tables.o", []))
     return units
 

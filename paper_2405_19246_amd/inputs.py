@@ -141,6 +141,14 @@ def merge_supports(supports, weights):
     return x, u
 
 
+def random_2d_marginals(N: int, M: int, seed: int = 0) -> np.ndarray:
+    """Sec. 5.3's recipe on an N x M grid: three arrays of i.i.d. U[0, 1] entries,
+    each normalised; shape [3][M][N] (entry (i1, i2) at [q, i2, i1])."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 2**31 - 3])))
+    u = rng.uniform(0.0, 1.0, size=(3, M, N))
+    return u / u.reshape(3, -1).sum(axis=1)[:, None, None]
+
+
 # Named workloads.  Each entry: l, N, K, eps, floor, uniform_frac.
 WORKLOADS = {
     # plain method: l=3, N=64, 2 components, eps=0.1, fixed 500 sweeps

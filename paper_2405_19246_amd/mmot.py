@@ -33,6 +33,10 @@ class Problem(ctypes.Structure):
                 ("x", ctypes.POINTER(_c_d))]
 
 
+class Problem2D(ctypes.Structure):
+    _fields_ = [("N", _c_i64), ("M", _c_i64), ("h1", _c_d), ("h2", _c_d), ("eps", _c_d)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("tol", _c_d), ("itr_max", _c_i64), ("check_every", _c_i32), ("flags", _c_i32)]
 
@@ -78,7 +82,9 @@ REQUEST_FN = ctypes.CFUNCTYPE(ctypes.c_int, _c_p, _c_i64, ctypes.POINTER(Request
 EXPORTS = ["mmot_plan", "mmot_plan_footprint", "mmot_plan_destroy", "mmot_marginal_product", "mmot_sinkhorn_iter",
            "mmot_solve", "mmot_objective", "mmot_marginal_errors", "mmot_solve_batch", "mmot_serve_start",
            "mmot_serve_submit", "mmot_serve_poll", "mmot_serve_stop", "mmot_serve_cancel", "mmot_serve", "mmot_last_batch_kernel_ms",
-           "mmot_last_batch_timing", "mmot_marginal_product_noalloc", "mmot_last_error"]
+           "mmot_last_batch_timing", "mmot_marginal_product_noalloc", "mmot_plan_2d", "mmot_plan_2d_destroy",
+           "mmot_marginal_product_2d", "mmot_solve_2d", "mmot_objective_2d", "mmot_marginal_errors_2d",
+           "mmot_last_error"]
 
 
 class MmotError(RuntimeError):
@@ -123,6 +129,12 @@ def lib() -> ctypes.CDLL:
         L.mmot_last_batch_kernel_ms.argtypes = [PP(_c_d)]
         L.mmot_last_batch_timing.argtypes = [PP(BatchTiming)]
         L.mmot_marginal_product_noalloc.argtypes = [PP(Problem), _c_i32, _c_p, _c_p, _c_p]
+        L.mmot_plan_2d.argtypes = [PP(Problem2D), PP(Opts), _c_p, PP(_c_p)]
+        L.mmot_plan_2d_destroy.argtypes = [_c_p]
+        L.mmot_marginal_product_2d.argtypes = [_c_p, _c_i32, _c_p, _c_p]
+        L.mmot_solve_2d.argtypes = [_c_p, _c_p, _c_p, PP(Result)]
+        L.mmot_objective_2d.argtypes = [_c_p, _c_p, PP(_c_d)]
+        L.mmot_marginal_errors_2d.argtypes = [_c_p, _c_p, _c_p, PP(_c_d)]
         L.mmot_last_error.argtypes = []
         L.mmot_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
@@ -244,6 +256,63 @@ class Plan:
         pa = _dev_f64(log_phi, (self.l, self.N), "log_phi")
         err = (_c_d * self.l)()
         _check(lib().mmot_marginal_errors(self._h, _c_p(pu), _c_p(pa), err))
+        return np.array(list(err))
+
+
+class Plan2D:
+    """Three marginals on an N x M grid with separable L1 cost (mmot_plan_2d), FP64.
+    Arrays are device float64 tensors [3][M][N] (potentials, marginals) or [M][N]."""
+
+    def __init__(self, N: int, M: int, h1: float, h2: float, eps: float, tol: float = 1e-8, itr_max: int = 1000,
+                 check_every: int = 10, warm_start: bool = False, stream=None):
+        self.N, self.M = int(N), int(M)
+        p = Problem2D(self.N, self.M, float(h1), float(h2), float(eps))
+        o = Opts(float(tol), int(itr_max), int(check_every), FLAG_WARM_START if warm_start else 0)
+        h = _c_p()
+        _check(lib().mmot_plan_2d(ctypes.byref(p), ctypes.byref(o), _c_p(_stream_handle(stream)), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mmot_plan_2d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def marginal_product(self, j: int, log_phi, out=None):
+        import torch
+        pa = _dev_f64(log_phi, (3, self.M, self.N), "log_phi")
+        if out is None:
+            out = torch.empty((self.M, self.N), dtype=torch.float64, device=log_phi.device)
+        po = _dev_f64(out, (self.M, self.N), "out")
+        _check(lib().mmot_marginal_product_2d(self._h, int(j), _c_p(pa), _c_p(po)))
+        return out
+
+    def solve(self, log_u, log_phi=None):
+        import torch
+        pu = _dev_f64(log_u, (3, self.M, self.N), "log_u")
+        if log_phi is None:
+            log_phi = torch.empty((3, self.M, self.N), dtype=torch.float64, device=log_u.device)
+        pa = _dev_f64(log_phi, (3, self.M, self.N), "log_phi")
+        r = Result()
+        _check(lib().mmot_solve_2d(self._h, _c_p(pu), _c_p(pa), ctypes.byref(r)), allow=(OK, NOT_CONVERGED))
+        return log_phi, r.as_dict()
+
+    def objective(self, log_phi) -> float:
+        pa = _dev_f64(log_phi, (3, self.M, self.N), "log_phi")
+        W = _c_d()
+        _check(lib().mmot_objective_2d(self._h, _c_p(pa), ctypes.byref(W)))
+        return W.value
+
+    def marginal_errors(self, log_u, log_phi) -> np.ndarray:
+        pu = _dev_f64(log_u, (3, self.M, self.N), "log_u")
+        pa = _dev_f64(log_phi, (3, self.M, self.N), "log_phi")
+        err = (_c_d * 3)()
+        _check(lib().mmot_marginal_errors_2d(self._h, _c_p(pu), _c_p(pa), err))
         return np.array(list(err))
 
 

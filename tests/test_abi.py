@@ -132,3 +132,16 @@ def test_jacobi_flag_is_a_plan_option():
     res = (mmot.Result * 1)()
     assert mmot.lib().mmot_solve_batch(arr, 1, 1, ctypes.byref(o), None, res) == -5
     assert "JACOBI" in mmot.last_error()
+
+
+def test_plan_2d_rejects_bad_shapes_before_device_work():
+    mmot = _lib()
+    out = ctypes.c_void_p()
+    for args in [(0, 4, 0.1, 0.1, 0.1), (4, 0, 0.1, 0.1, 0.1), (4, 4, 0.0, 0.1, 0.1), (4, 4, 0.1, -1.0, 0.1),
+                 (4, 4, 0.1, 0.1, 0.0), (1 << 20, 1 << 20, 0.1, 0.1, 0.1)]:
+        p = mmot.Problem2D(*args)
+        assert mmot.lib().mmot_plan_2d(ctypes.byref(p), None, None, ctypes.byref(out)) == -1
+        assert out.value is None
+    p = mmot.Problem2D(4, 4, 0.1, 0.1, 0.1)
+    o = mmot.Opts(1e-6, 10, 10, mmot.FLAG_TILES)
+    assert mmot.lib().mmot_plan_2d(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(out)) == -5
