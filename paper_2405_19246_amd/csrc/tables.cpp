@@ -199,7 +199,7 @@ int tile_candidates(int l, int64_t N, int flags, int *cand)
         return 1;
     }
     int k = 0;
-    for (int c : {b / 4, b / 2, b, 2 * b})
+    for (int c : {b / 8, b / 4, b / 2, b, 2 * b})
         if (c >= 64 && c <= 8192) cand[k++] = c;
     return k;
 }
@@ -221,7 +221,7 @@ size_t tile_scratch_bytes(int l, int64_t N, int ntile, int B)
     // room for every length the autotuner may pick for this N
     (void)ntile;
     (void)B;
-    int cand[4];
+    int cand[5];
     const int k = tile_candidates(l, N, F_TILE_SMALL, cand);
     size_t best = 0;
     for (int i = 0; i < k; ++i) best = std::max(best, carve(l, (int)((N + cand[i] - 1) / cand[i]), cand[i]).total);

@@ -96,12 +96,12 @@ const int *tile_group_list(const BatchBuffers *bb, const TileJobs &J)
 // Autotuner of the tile length.  For an instance whose (l, ceil(log2 N)) class
 // has no measured length yet: its potentials are initialised as the solve would
 // (phi = 1/N unless warm), then one tiled FP64 check pass of marginal 0 runs at
-// each candidate length (a quarter, half, once and twice the rule's; warm-up run, then a run
+// each candidate length (an eighth, a quarter, half, once and twice the rule's; warm-up run, then a run
 // timed with HIP events on the stream), and the fastest is kept for the class.
 static int tune_tile_length(int l, int i, int count, const Inst *hI, const Ptrs *hP, const RunOpts &o, int flags,
                             hipStream_t s, BatchBuffers *bb)
 {
-    int cand[4];
+    int cand[5];
     const int k = tile_candidates(l, hI[i].N, flags | hP[i].flags, cand);
     if (k <= 1) {
         if (k == 1) tile_set_tuned(l, hI[i].N, cand[0]);

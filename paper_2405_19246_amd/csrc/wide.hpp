@@ -66,6 +66,40 @@ struct WL {
     static constexpr int CK = wide_ck(L, EWords<E>::n);  // positions per recompute block
 };
 
+// ---- global memory through global-address-space pointers -------------------------
+// A load or store through a generic pointer compiles to a flat instruction, which
+// also counts against the LDS wait counter: every LDS read after it would wait for
+// the global access to land.  The walks' global accesses go through these.
+template <typename T>
+__device__ __forceinline__ T gld(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T *p, T v)
+{
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+// element kinds (XF, DXF) word by word
+template <typename E>
+__device__ __forceinline__ E gld_e(const E *p)
+{
+    E v;
+    int *d = reinterpret_cast<int *>(&v);
+    const __attribute__((address_space(1))) int *q = (const __attribute__((address_space(1))) int *)p;
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(E) / 4); ++w) d[w] = q[w];
+    return v;
+}
+template <typename E>
+__device__ __forceinline__ void gst_e(E *p, E v)
+{
+    const int *d = reinterpret_cast<const int *>(&v);
+    __attribute__((address_space(1))) int *q = (__attribute__((address_space(1))) int *)p;
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(E) / 4); ++w) q[w] = d[w];
+}
+
 // ---- lane moves inside a team ---------------------------------------------------
 // UP = false: the value of lane t - 2^B; UP = true: of lane t + 2^B.  Only lanes
 // whose source lies in the same team use the result.
@@ -113,13 +147,32 @@ __device__ __forceinline__ XF<M> esel(bool c, XF<M> a, XF<M> b)
 }
 __device__ __forceinline__ DXF esel(bool c, DXF a, DXF b) { return {esel(c, a.v, b.v), esel(c, a.w, b.w)}; }
 
-// Wavefront-local ordering of LDS and global accesses between the lanes of a
-// team (one team never spans more than a wavefront).
+// Wavefront-local ordering of the LDS accesses between the lanes of a team (one
+// team never spans more than a wavefront).  The fences cover LDS only: the
+// walks' global loads and stores are each used by the lane that issued them, so
+// a team_sync need not wait for them to land.
 __device__ __forceinline__ void team_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// As team_sync, also ordering global memory: for global data one lane writes and
+// other lanes of the team read later in the same launch (potentials).
+__device__ __forceinline__ void team_sync_global()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Workgroup barrier ordering LDS only (as team_sync, for a whole workgroup).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Per-lane constants of one walk: g(level) for the levels this lane's registers
@@ -226,6 +279,7 @@ struct WTeam {
     XG<M> *gt;             // LDS [CK + 1][l + 1] gap factors g(level) of the staged block (row s:
                            // the gap before its position s); one row on the uniform grid
     double *gd;            // LDS [CK + 1] those gaps' lengths (non-uniform grid)
+    double *vj, *vu;       // LDS [CK] a_j and log u_j at the staged block's positions
     E *ck;                 // scratch: checkpoints [blocks][D]
 };
 
@@ -234,10 +288,12 @@ struct WTeam {
 // With them the gap factors g_s(level) = exp(-d_s level (l - level) / eps) of the
 // gaps d_s between positions x0 + s - 1 and x0 + s, s = 0..cnt (a gap outside
 // [0, N) has length 0): on the uniform grid every gap is h and one row, from
-// h / eps, serves the whole block.
+// h / eps, serves the whole block.  With stage_j, also a_j (and log u_j if
+// log_u is given) at the block's positions, for the combine's epilogue.
 template <int L, typename E>
 __device__ __forceinline__ void stage_phi(const WTeam<L, E> &tm, const Inst *__restrict__ I,
-                                          const double *__restrict__ a, int j, long x0, int cnt)
+                                          const double *__restrict__ a, int j, long x0, int cnt,
+                                          bool stage_j = false, const double *__restrict__ log_u = nullptr)
 {
     using W = WL<L, E>;
     using M = typename ET<E>::MT;
@@ -247,9 +303,14 @@ __device__ __forceinline__ void stage_phi(const WTeam<L, E> &tm, const Inst *__r
         const int s = k / W::n, r = k - s * W::n;
         const int q = r < j ? r : r + 1;
         XF<M> v = xzero<M>();
-        if (s < cnt) v = xfrom_log<M>(a[(long)q * N + x0 + s]);
+        if (s < cnt) v = xfrom_log<M>(gld(&a[(long)q * N + x0 + s]));
         tm.ph[s * W::n + r] = v;
     }
+    if (stage_j)
+        for (int s = tm.t; s < cnt; s += W::TL) {
+            tm.vj[s] = gld(&a[(long)j * N + x0 + s]);
+            if (log_u) tm.vu[s] = gld(&log_u[(long)j * N + x0 + s]);
+        }
     const double *xs = I->x;
     const int rows = xs ? cnt + 1 : 1;
     for (int k = tm.t; k < rows * (L + 1); k += W::TL) {
@@ -257,7 +318,7 @@ __device__ __forceinline__ void stage_phi(const WTeam<L, E> &tm, const Inst *__r
         double lg;
         if (xs) {
             const long p = x0 + s;
-            const double d = (p >= 1 && p < N) ? xs[p] - xs[p - 1] : 0.0;
+            const double d = (p >= 1 && p < N) ? gld(&xs[p]) - gld(&xs[p - 1]) : 0.0;
             if (lev == 0) tm.gd[s] = d;
             lg = -(double)(lev * (L - lev)) * (d * I->ieps);
         } else {
@@ -326,13 +387,13 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
 #pragma unroll
     for (int i = 0; i < RG; ++i) {
         const int S = i * W::TL + t;
-        A[i] = cf ? cf[S] : esel(S == 0, T_::one(), T_::zero());
+        A[i] = cf ? gld_e(&cf[S]) : esel(S == 0, T_::one(), T_::zero());
     }
     for (long b = 0; b < nblk; ++b) {
         const long x0 = p0 + b * CK;
         const int cnt = (int)min((long)CK, p1 - x0);
 #pragma unroll
-        for (int i = 0; i < RG; ++i) tm.ck[b * D + i * W::TL + t] = A[i];
+        for (int i = 0; i < RG; ++i) gst_e(&tm.ck[b * D + i * W::TL + t], A[i]);
         if (b == nblk - 1) break;  // the last block's forward states are recomputed below
         stage_phi<L, E>(tm, I, a, j, x0, cnt);
         for (int s = 0; s < cnt; ++s) wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt, 1), t);
@@ -344,16 +405,17 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
 #pragma unroll
     for (int i = 0; i < RG; ++i) {
         const int S = i * W::TL + t;
-        Bs[i] = cb ? cb[S] : esel(S == D - 1, T_::one(), T_::zero());
+        Bs[i] = cb ? gld_e(&cb[S]) : esel(S == D - 1, T_::one(), T_::zero());
     }
     for (long b = nblk - 1; b >= 0; --b) {
         const long x0 = p0 + b * CK;
         const int cnt = (int)min((long)CK, p1 - x0);
-        stage_phi<L, E>(tm, I, a, j, x0, cnt);
+        stage_phi<L, E>(tm, I, a, j, x0, cnt, MODE != P_PRODUCT,
+                        (MODE == P_UPDATE || MODE == P_CHECK) ? log_u : nullptr);
         // forward states of the block
         E F[CK][RG];
 #pragma unroll
-        for (int i = 0; i < RG; ++i) A[i] = tm.ck[b * D + i * W::TL + t];
+        for (int i = 0; i < RG; ++i) A[i] = gld_e(&tm.ck[b * D + i * W::TL + t]);
 #pragma unroll
         for (int s = 0; s < CK; ++s) {
             if (s < cnt) wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt, 1), t);
@@ -375,17 +437,25 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
             }
             const E J = team_total<L, E>(part, t);
             if (tm.last) {
+                // the epilogue of finish_lj, with a_j and log u_j from the staged block
                 if constexpr (MODE == P_OBJECTIVE) {
-                    const XF<double> ph = xfrom_log<double>(a[(long)j * N + y]);
+                    const XF<double> ph = xfrom_log<double>(tm.vj[s]);
                     acc.x = xadd(acc.x, xmul(ph, J.w));
+                } else if constexpr (MODE == P_PRODUCT) {
+                    gst(&out[y], xto_log(J));
+                } else if constexpr (MODE == P_UPDATE) {
+                    const double lj = xto_log(J), lu = tm.vu[s], ao = tm.vj[s];
+                    const double an = lu > -INFINITY ? lu - lj : -INFINITY;
+                    gst(&a[(long)j * N + y], an);
+                    acc.s += lu > -INFINITY ? exp(lu) * fabs(expm1(ao - an)) : 0.0;
                 } else {
-                    acc.s += finish_lj<MODE>(xto_log(J), j, N, y, a, log_u, out);
+                    acc.s += fabs(exp(tm.vj[s] + xto_log(J)) - exp(tm.vu[s]));
                 }
             }
             wstep<L, E, true>(Bs, tm.ph + s * n, cB, t);
         }
     }
-    team_sync();
+    team_sync_global();  // a_j written by the last lane is read by every lane in the next pass
     return acc;
 }
 
@@ -438,7 +508,8 @@ struct WShared {
                                                                            : WL<L, XF<double>>::CK;
     static constexpr int ROWS = (C1 > WL<L, DXF>::CK ? C1 : WL<L, DXF>::CK) + 1;
     static constexpr int GT = ROWS * (L + 1) * (int)sizeof(XG<double>);
-    static constexpr int BYTES = (PH + GT + ROWS * (int)sizeof(double) + 15) / 16 * 16;
+    // gap lengths [ROWS], a_j and log u_j [ROWS] each
+    static constexpr int BYTES = (PH + GT + 3 * ROWS * (int)sizeof(double) + 15) / 16 * 16;
     static constexpr int TPWMAX = WL<L, XF<float>>::TPW;  // TL does not depend on the element kind
 };
 
@@ -457,6 +528,8 @@ __device__ __forceinline__ WTeam<L, E> make_team(char *lds, void *scratch)
     tm.ph = reinterpret_cast<XF<typename ET<E>::MT> *>(base);
     tm.gt = reinterpret_cast<XG<typename ET<E>::MT> *>(base + WShared<L>::PH);
     tm.gd = reinterpret_cast<double *>(base + WShared<L>::PH + WShared<L>::GT);
+    tm.vj = tm.gd + WShared<L>::ROWS;
+    tm.vu = tm.vj + WShared<L>::ROWS;
     tm.ck = reinterpret_cast<E *>(scratch);
     return tm;
 }
@@ -483,7 +556,7 @@ __device__ void wide_solve(char *lds, const Inst *__restrict__ I, const Ptrs P, 
         // phi = 1/N (Alg. 1 initialisation)
         const double a0 = -log((double)N);
         for (long p = tu.t; p < (long)L * N; p += TL) a[p] = a0;
-        team_sync();
+        team_sync_global();
     }
     long it = P.it0;
     int jr = P.j0;
@@ -650,7 +723,7 @@ __device__ void tile_agg_job(const WTeam<L, E> &tm, const Inst *__restrict__ I, 
     }
     E *q = reinterpret_cast<E *>(T.agg) + (((long)t * 2 + dir) * L + m) * D;
 #pragma unroll
-    for (int i = 0; i < RG; ++i) q[i * W::TL + tm.t] = A[i];
+    for (int i = 0; i < RG; ++i) gst_e(&q[i * W::TL + tm.t], A[i]);
     team_sync();
 }
 
@@ -695,24 +768,63 @@ __host__ __device__ constexpr int chain_items(int n)
     return tot;
 }
 
+// Element kinds in LDS as word planes: word w of element i at plane[w][i], so
+// that lanes reading neighbouring elements hit neighbouring banks (a 16-byte
+// struct stride puts a wavefront's reads on a quarter of the banks).  Only the
+// words that carry data are stored (not the padding of XF<double>).
+template <typename E>
+struct Words;
+template <>
+struct Words<XF<float>> {
+    static constexpr int NW = 2;
+    static constexpr int at(int k) { return k; }
+};
+template <>
+struct Words<XF<double>> {
+    static constexpr int NW = 3;
+    static constexpr int at(int k) { return k; }
+};
+template <>
+struct Words<DXF> {
+    static constexpr int NW = 6;
+    static constexpr int at(int k) { return k < 3 ? k : k + 1; }
+};
+
+template <typename E, int COUNT>
+__device__ __forceinline__ E pl_load(const int *pl, int i)
+{
+    E v;
+    int *d = reinterpret_cast<int *>(&v);
+#pragma unroll
+    for (int k = 0; k < Words<E>::NW; ++k) d[Words<E>::at(k)] = pl[k * COUNT + i];
+    return v;
+}
+template <typename E, int COUNT>
+__device__ __forceinline__ void pl_store(int *pl, int i, E v)
+{
+    const int *d = reinterpret_cast<const int *>(&v);
+#pragma unroll
+    for (int k = 0; k < Words<E>::NW; ++k) pl[k * COUNT + i] = d[Words<E>::at(k)];
+}
+
 // The hop's aggregates are staged in LDS when they fit beside the rest.
 template <int L, typename E>
 constexpr bool chain_stages()
 {
-    return sizeof(E) * (size_t)L * WL<L, E>::D + sizeof(E) * (size_t)(WL<L, E>::D + chain_items(L - 1)) +
+    return (size_t)4 * Words<E>::NW * ((size_t)L * WL<L, E>::D + WL<L, E>::D + chain_items(L - 1)) +
                sizeof(int) * (size_t)chain_items(L - 1) <=
            (size_t)136 * 1024;
 }
 
-// Carries from tile to tile in one direction, one workgroup per (instance,
-// direction).  In subset space (forward: S as held; backward: the complement of
-// the index), c_next(S) = sum_{S' subset S} c(S') Q_{|S'|}(S \ S') with c(empty) = 1.
-// The 3^(l-1) terms of a hop are dealt to the threads as work items of at most
-// CHAIN_CHUNK subsets S' of one S (S' walked downwards from a stored start);
-// each item's partial sum goes to LDS and a second phase adds the items of each
-// S.  The tile's l 2^(l-1) aggregates are read into registers during the previous
-// hop and stored to LDS at the start of their own, so a hop waits on no global
-// load.
+// Carries from tile to tile in one direction, one workgroup of CHAIN_THREADS per
+// (instance, direction).  In subset space (forward: S as held; backward: the
+// complement of the index), c_next(S) = sum_{S' subset S} c(S') Q_{|S'|}(S \ S')
+// with c(empty) = 1.  The 3^(l-1) terms of a hop are dealt to the threads as work
+// items of at most CHAIN_CHUNK subsets S' of one S (S' walked downwards from a
+// stored start); each item's partial sum goes to LDS and a second phase adds the
+// items of each S.  The tile's l 2^(l-1) aggregates are read into registers
+// during the previous hop and stored to LDS at the start of their own, so a hop
+// waits on no global load.
 template <int L, typename E>
 __global__ __launch_bounds__(CHAIN_THREADS) void k_tile_chain(const TileInst *TI, const TileTrack *Tr,
                                                               const int2 *jobs, int njobs, int state_need)
@@ -724,85 +836,129 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_tile_chain(const TileInst *TI
     constexpr bool STAGE = chain_stages<L, E>();
     constexpr int QN = L * D;
     constexpr int PF = STAGE ? (QN + CHAIN_THREADS - 1) / CHAIN_THREADS : 1;
-    __shared__ E c[D];
-    __shared__ E part[MAXI];
+    constexpr int NW = Words<E>::NW;
+    __shared__ int c[NW * D];
+    __shared__ int part[NW * MAXI];
     __shared__ int item[MAXI];  // S | start S' << 10 | count << 20
     __shared__ int ioff[D + 1];
-    __shared__ E qs[STAGE ? QN : 1];
+    __shared__ int qs[STAGE ? NW * QN : 1];
+    // The hop reads aggregate rank m D + subset; D is a multiple of the 32 LDS banks
+    // and many of the subsets read together are multiples of 32 too, so the plain
+    // index would pile a wavefront's reads onto bank 0.  The staged copy lives at
+    // a swizzled index: the low five bits XOR-ed with the next ten (a permutation
+    // inside every aligned group of 32, so inside [0, QN) when QN is a multiple of 32).
+    auto qsw = [](int i) { return (QN % 32 == 0) ? i ^ (((i >> 5) ^ (i >> 10)) & 31) : i; };
+    // the carries likewise (the subsets read together are often multiples of 32)
+    auto csw = [](int i) { return (D % 32 == 0) ? i ^ ((i >> 5) & 31) : i; };
     const int2 jb = jobs[blockIdx.x];
     if (Tr && Tr[jb.x].state != state_need) return;
     const TileInst T = TI[jb.x];
     const int dir = jb.y;
     const int tid = threadIdx.x;
     auto idx = [&](int S) { return dir == 0 ? S : (D - 1) ^ S; };
+    // item table: offsets by a prefix sum of the per-state counts, then every
+    // thread lists its own states' items (subsets of S in decreasing order,
+    // CHAIN_CHUNK at a time)
+    for (int S = tid; S < D; S += blockDim.x) ioff[S + 1] = ((1 << popc(S)) + CHAIN_CHUNK - 1) / CHAIN_CHUNK;
+    lds_barrier();
     if (tid == 0) {
-        int o = 0;
-        for (int S = 0; S < D; ++S) {
-            ioff[S] = o;
-            // subsets of S in decreasing order, CHAIN_CHUNK at a time
-            int Sp = S, left = 1 << popc(S);
-            while (left > 0) {
-                const int cnt = min(CHAIN_CHUNK, left);
-                item[o++] = S | (Sp << 10) | (cnt << 20);
-                for (int k = 0; k < cnt; ++k) Sp = (Sp - 1) & S;
-                left -= cnt;
-            }
-        }
-        ioff[D] = o;
+        ioff[0] = 0;
+        for (int S = 0; S < D; ++S) ioff[S + 1] += ioff[S];
     }
-    for (int S = tid; S < D; S += blockDim.x) c[S] = esel(S == 0, T_::one(), T_::zero());
+    lds_barrier();
+    for (int S = tid; S < D; S += blockDim.x) {
+        int o = ioff[S], Sp = S, left = 1 << popc(S);
+        while (left > 0) {
+            const int cnt = min(CHAIN_CHUNK, left);
+            item[o++] = S | (Sp << 10) | (cnt << 20);
+            for (int k = 0; k < cnt; ++k) Sp = (Sp - 1) & S;
+            left -= cnt;
+        }
+    }
+    for (int S = tid; S < D; S += blockDim.x) pl_store<E, D>(c, csw(S), esel(S == 0, T_::one(), T_::zero()));
     E *carry = reinterpret_cast<E *>(T.carry);
     const E *agg = reinterpret_cast<const E *>(T.agg);
     auto hop_q = [&](int s) { return agg + ((long)(dir == 0 ? s : T.ntile - 1 - s) * 2 + dir) * QN; };
-    // prefetch registers: entry k of this thread is aggregate min(tid + k 512, QN - 1),
-    // moved as 32-bit words (a struct copy with padding would go through scratch)
-    constexpr int WD = (int)(sizeof(E) / 4);
-    int pre[PF][WD];
+    // prefetch registers: the data words of aggregate min(tid + k 512, QN - 1), read
+    // through a global-address-space pointer (a flat load would also count
+    // against the LDS wait counter and stall every LDS read of the hop until it
+    // landed)
+    using GInt = const __attribute__((address_space(1))) int;
+    int pre[PF][NW];
     auto fetch = [&](const E *q) {
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
-            const int *src = reinterpret_cast<const int *>(q + min(tid + k * CHAIN_THREADS, QN - 1));
+            GInt *src = (GInt *)(q + min(tid + k * CHAIN_THREADS, QN - 1));
 #pragma unroll
-            for (int w = 0; w < WD; ++w) pre[k][w] = src[w];
+            for (int w = 0; w < NW; ++w) pre[k][w] = src[Words<E>::at(w)];
         }
     };
     if (STAGE && T.ntile > 1) fetch(hop_q(0));
-    __syncthreads();
+    lds_barrier();
     for (int s = 0; s < T.ntile; ++s) {
         const int t = dir == 0 ? s : T.ntile - 1 - s;
-        for (int S = tid; S < D; S += blockDim.x) carry[((long)t * 2 + dir) * D + idx(S)] = c[S];
+        for (int S = tid; S < D; S += blockDim.x)
+            gst_e(&carry[((long)t * 2 + dir) * D + idx(S)], pl_load<E, D>(c, csw(S)));
         if (s == T.ntile - 1) break;
-        const E *q = hop_q(s);
+        const E *qg = hop_q(s);  // the hop's aggregates in global memory (used when not staged)
         if (STAGE) {
 #pragma unroll
             for (int k = 0; k < PF; ++k)
                 if (tid + k * CHAIN_THREADS < QN) {
-                    int *dst = reinterpret_cast<int *>(qs + tid + k * CHAIN_THREADS);
 #pragma unroll
-                    for (int w = 0; w < WD; ++w) dst[w] = pre[k][w];
+                    for (int w = 0; w < NW; ++w) qs[w * QN + qsw(tid + k * CHAIN_THREADS)] = pre[k][w];
                 }
-            __syncthreads();
+            lds_barrier();
             fetch(hop_q(min(s + 1, T.ntile - 2)));
-            q = qs;
         }
+        auto qat = [&](int i) -> E {
+            if constexpr (STAGE) {
+                return pl_load<E, QN>(qs, qsw(i));
+            } else {
+                E v;
+                int *d = reinterpret_cast<int *>(&v);
+                GInt *src = (GInt *)(qg + i);
+#pragma unroll
+                for (int w = 0; w < NW; ++w) d[Words<E>::at(w)] = src[Words<E>::at(w)];
+                return v;
+            }
+        };
         for (int it = tid; it < ioff[D]; it += blockDim.x) {
             const int w = item[it];
             const int S = w & 1023, cnt = w >> 20;
             int Sp = (w >> 10) & 1023;
-            E acc = T_::zero();
-            for (int k = 0; k < cnt; ++k) {
-                acc = chain_mac(acc, c[Sp], q[popc(Sp) * D + idx(S ^ Sp)]);
+            // all of the item's LDS reads first (terms past cnt read entry 0 and are
+            // skipped), then the multiply-adds on two independent accumulators
+            E cv[CHAIN_CHUNK], qv[CHAIN_CHUNK];
+#pragma unroll
+            for (int k = 0; k < CHAIN_CHUNK; ++k) {
+                const int s2 = k < cnt ? Sp : 0;
+                cv[k] = pl_load<E, D>(c, csw(s2));
+                qv[k] = qat(popc(s2) * D + idx(S ^ s2));
                 Sp = (Sp - 1) & S;
             }
-            part[it] = xnorm(acc);
+            E acc0 = T_::zero(), acc1 = T_::zero();
+#pragma unroll
+            for (int k = 0; k < CHAIN_CHUNK; k += 2) {
+                if (k < cnt) acc0 = chain_mac(acc0, cv[k], qv[k]);
+                if (k + 1 < cnt) acc1 = chain_mac(acc1, cv[k + 1], qv[k + 1]);
+            }
+            pl_store<E, MAXI>(part, it, xnorm(T_::add(xnorm(acc0), xnorm(acc1))));
         }
-        __syncthreads();
+        lds_barrier();
+        // the items of each state, four reads at a time
         for (int S = tid; S < D; S += blockDim.x) {
-            E acc = part[ioff[S]];
-            for (int it = ioff[S] + 1; it < ioff[S + 1]; ++it) acc = T_::add(acc, part[it]);
-            c[S] = acc;
+            const int b = ioff[S], e = ioff[S + 1];
+            E acc = pl_load<E, MAXI>(part, b);
+            for (int it = b + 1; it < e; it += 4) {
+                E v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = (it + u < e) ? pl_load<E, MAXI>(part, it + u) : T_::zero();
+                acc = T_::add(acc, T_::add(T_::add(v[0], v[1]), T_::add(v[2], v[3])));
+            }
+            pl_store<E, D>(c, csw(S), acc);
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -830,7 +986,7 @@ __global__ __launch_bounds__(64) void k_tile_final(const Inst *I, const Ptrs *P,
     const E *carry = reinterpret_cast<const E *>(T.carry);
     const WAcc r = wide_pass<L, E, MODE>(tm, In, j, Pp.a, Pp.log_u, Pp.out, p0, p1, carry + ((long)t * 2 + 0) * D,
                                          carry + ((long)t * 2 + 1) * D);
-    if (tm.last) T.part[(long)j * T.ntile + t] = (MODE == P_OBJECTIVE) ? In->h * xto_double(r.x) : r.s;
+    if (tm.last) gst(&T.part[(long)j * T.ntile + t], (MODE == P_OBJECTIVE) ? In->h * xto_double(r.x) : r.s);
 }
 
 // After the update passes of a sweep: the estimate, then whether a residual

@@ -76,6 +76,27 @@ def test_batch_equals_single_solve_bitwise():
         assert rs["W"] == r["W"]
 
 
+@pytest.mark.parametrize("prec", ["FP32", "FP64"])
+def test_fast_path_instance_alone_equals_sharing_rounds_with_a_longer_one(prec):
+    # the register-resident kernels size a group's workgroups for its longest
+    # instance: an N = 64 solve alone runs on one wavefront, beside an N = 1000
+    # one on four (padding positions carry zero mass); its iterates, sweep count
+    # and objective must not change
+    mmot = _mmot()
+    pr = getattr(mmot, prec)
+    small = dict(l=4, N=64, h=inputs.grid_step(64), eps=0.05, u=inputs.marginals(4, 64, K=2, master_seed=31))
+    big = dict(l=4, N=1000, h=inputs.grid_step(1000), eps=0.01, u=inputs.marginals(4, 1000, K=3, master_seed=32))
+    say("fast path alone vs shared rounds, %s" % prec)
+    alone = _device_instances([dict(small)])
+    ra = mmot.solve_batch(alone, precision=pr, tol=1e-6 if prec == "FP32" else 1e-9, itr_max=20000, check_every=0)
+    mix = _device_instances([dict(big), dict(small), dict(big)])
+    rm = mmot.solve_batch(mix, precision=pr, tol=1e-6 if prec == "FP32" else 1e-9, itr_max=20000, check_every=0)
+    t = mmot.last_batch_timing()
+    assert t["sweep_launches"] > 0  # the register-resident path ran
+    assert rm[1]["iters"] == ra[0]["iters"] and rm[1]["W"] == ra[0]["W"]
+    assert np.array_equal(mix[1]["log_phi"].cpu().numpy(), alone[0]["log_phi"].cpu().numpy())
+
+
 def test_server_mix_equals_alone():
     # a request gives the same result alone and while sharing rounds with others
     mmot = _mmot()
