@@ -21,7 +21,8 @@ traffic is attached while the kernel sources match the profiled ones.
 Extra fields (skipped with --no-extras): the same batch in FP64 to 1e-8; the
 plain configuration (l = 3, N = 64, eps = 0.1, 500 FP64 sweeps, 10 seeds); the
 l = 10, N = 1e5, eps = 1e-3 shape (a few tiled sweeps); the Ricker-wavelet
-problem (Table 2's sizes, time to each marginal error at N = 80); the batch on the
+problem (Table 2's sizes, time to each marginal error at N = 80); the 2-D problem (Table 3's
+sizes), a non-uniform grid and the Jacobi sweep; the batch on the
 one-wavefront solver; one solve per call; continuous-batching serving runs
 (the headline shape, and the mixed request stream with l up to 16 and N up to
 1e6, cancelled after a fixed window); the oracle timed on the host cores.
@@ -257,6 +258,53 @@ def ricker(dev):
     return {"table2_eps0.1_100_sweeps": table2, "fig2a_n80": fig2a}
 
 
+def next_rows(dev):
+    """The rows built around the hot path, each timed once (FP64, one solve per call).
+
+    twod: three marginals on an N x N grid (Sec. 5.3: U[0, 1] entries), eps = 0.1,
+    100 sweeps; grid: l = 4, N = 1000, eps = 1e-2 on a graded non-uniform grid
+    to Res <= 1e-8, beside the same marginals on the uniform grid; jacobi: the
+    all-marginals sweep against Gauss-Seidel, l = 4, N = 300, eps = 0.05, to 1e-9."""
+    import torch
+    from paper_2405_19246_amd import inputs, mmot
+
+    def t64(x):
+        return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+    twod = {}
+    for N in (10, 20, 40, 80, 160):
+        u = inputs.random_2d_marginals(N, N, seed=N)
+        h = 1.0 / (N - 1)
+        plan = mmot.Plan2D(N, N, h, h, 0.1, tol=-1.0, itr_max=100)
+        lu = t64(np.log(u))
+        plan.solve(lu)
+        (lp, r), dt = timed(lambda: plan.solve(lu))
+        twod[str(N)] = dict(seconds=dt, sweeps=r["iters"], units_per_s=3 * N * N * r["iters"] / dt, W=r["W"])
+    grid = {}
+    l, N, eps = 4, 1000, 1e-2
+    x = inputs.graded_grid(N, seed=1)
+    for name, xs in (("graded", x), ("uniform", None)):
+        u = inputs.grid_marginals(xs, l, K=3, master_seed=3) if xs is not None else \
+            inputs.marginals(l, N, K=3, master_seed=3)
+        plan = mmot.Plan(l, N, inputs.grid_step(N), eps, precision=mmot.FP64, tol=1e-8, itr_max=100000,
+                         check_every=0, x=xs)
+        lu = t64(np.log(u))
+        plan.solve(lu)
+        (lp, r), dt = timed(lambda: plan.solve(lu))
+        grid[name] = dict(seconds=dt, sweeps=r["iters"], units_per_s=l * N * r["iters"] / dt, Res=r["marg_err"])
+    jac = {}
+    l, N, eps = 4, 300, 0.05
+    u = inputs.marginals(l, N, K=3, master_seed=2, instance=7)
+    lu = t64(np.log(u))
+    for name, jflag in (("jacobi", True), ("gauss_seidel", False)):
+        plan = mmot.Plan(l, N, inputs.grid_step(N), eps, precision=mmot.FP64, tol=1e-9, itr_max=200000,
+                         check_every=20, jacobi=jflag)
+        plan.solve(lu)
+        (lp, r), dt = timed(lambda: plan.solve(lu))
+        jac[name] = dict(seconds=dt, sweeps=r["iters"], Res=r["marg_err"], W=r["W"])
+    return {"twod_eps0.1_100_sweeps": twod, "grid_l4_n1000_eps0.01": grid, "jacobi_l4_n300_eps0.05": jac}
+
+
 def c4_batch(dev, count: int, itr_max: int):
     import torch
     from paper_2405_19246_amd import inputs, mmot
@@ -359,7 +407,7 @@ def main():
     ap.add_argument("--c4", type=int, default=0, metavar="COUNT",
                     help="also solve the first COUNT instances of the mixed batch configuration")
     ap.add_argument("--c4-itr-max", type=int, default=100000)
-    ap.add_argument("--only", choices=("plain", "l10", "serve_mixed", "ricker"),
+    ap.add_argument("--only", choices=("plain", "l10", "serve_mixed", "ricker", "next_rows"),
                     help="run only this extra leg and print its JSON (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 4 times (reference for HBM byte counters)")
@@ -394,7 +442,8 @@ def main():
     mmot.lib()
     if args.only:
         leg = {"plain": lambda: plain_config(dev), "l10": lambda: l10_shape(dev, 3),
-               "serve_mixed": lambda: serve_mixed(0.5, 8.0), "ricker": lambda: ricker(dev)}[args.only]()
+               "serve_mixed": lambda: serve_mixed(0.5, 8.0), "ricker": lambda: ricker(dev),
+               "next_rows": lambda: next_rows(dev)}[args.only]()
         print(json.dumps({"leg": args.only, **leg}), flush=True)
         return
     tol32, tol64 = 1e-6, 1e-8
@@ -474,6 +523,7 @@ def main():
         out["plain_config"] = plain_config(dev)
         out["l10_n100000_eps0.001"] = l10_shape(dev, 3)
         out["ricker"] = ricker(dev)
+        out["next_rows"] = next_rows(dev)
         (rx, tx) = timed(lambda: step(mmot.FP32, tol32, fast=False))
         out["one_wavefront_solver"] = dict(value=units_of(rx) / tx, seconds=tx,
                                            all_converged=all(r["status"] == 0 for r in rx),
