@@ -194,10 +194,15 @@ constexpr int wide_ck(int l, int words)
 {
     return 48 / (wide_rg(l) * words) < 1 ? 1 : (48 / (wide_rg(l) * words) > 16 ? 16 : 48 / (wide_rg(l) * words));
 }
+// Where blocks hold at most two positions the forward walk keeps the state after
+// every position (at most twice the memory of the block checkpoints) and the
+// backward walk reads it instead of recomputing it.
+constexpr bool wide_store_all(int l, int words) { return wide_ck(l, words) <= 2; }
 // checkpoint bytes of one pass over len positions
 constexpr long wide_ck_bytes(int l, int words, int bytes, long len)
 {
-    return ((len + wide_ck(l, words) - 1) / wide_ck(l, words)) * (long)wide_states(l) * (long)bytes;
+    return (wide_store_all(l, words) ? len : (len + wide_ck(l, words) - 1) / wide_ck(l, words)) *
+           (long)wide_states(l) * (long)bytes;
 }
 // checkpoint bytes of one instance: the largest over the FP32, FP64 and objective passes
 constexpr long wide_scratch_bytes(int l, long N)

@@ -64,6 +64,7 @@ struct WL {
     static constexpr int LB = ilog2c(TL);         // items held across lanes
     static constexpr int RB = ilog2c(RG);         // items held across registers
     static constexpr int CK = wide_ck(L, EWords<E>::n);  // positions per recompute block
+    static constexpr bool SA = wide_store_all(L, EWords<E>::n);  // forward states of every position kept
 };
 
 // ---- global memory through global-address-space pointers -------------------------
@@ -382,7 +383,7 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
     if (len <= 0) return acc;
     const long nblk = (len + CK - 1) / CK;
 
-    // forward walk, checkpoint before every block
+    // forward walk: the state before every block (W::SA: after every position)
     E A[RG];
 #pragma unroll
     for (int i = 0; i < RG; ++i) {
@@ -392,11 +393,19 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
     for (long b = 0; b < nblk; ++b) {
         const long x0 = p0 + b * CK;
         const int cnt = (int)min((long)CK, p1 - x0);
+        if constexpr (!W::SA) {
 #pragma unroll
-        for (int i = 0; i < RG; ++i) gst_e(&tm.ck[b * D + i * W::TL + t], A[i]);
-        if (b == nblk - 1) break;  // the last block's forward states are recomputed below
+            for (int i = 0; i < RG; ++i) gst_e(&tm.ck[b * D + i * W::TL + t], A[i]);
+            if (b == nblk - 1) break;  // the last block's forward states are recomputed below
+        }
         stage_phi<L, E>(tm, I, a, j, x0, cnt);
-        for (int s = 0; s < cnt; ++s) wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt, 1), t);
+        for (int s = 0; s < cnt; ++s) {
+            wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt, 1), t);
+            if constexpr (W::SA) {
+#pragma unroll
+                for (int i = 0; i < RG; ++i) gst_e(&tm.ck[(x0 - p0 + s) * D + i * W::TL + t], A[i]);
+            }
+        }
     }
     team_sync();
 
@@ -412,15 +421,23 @@ __device__ WAcc wide_pass(const WTeam<L, E> &tm, const Inst *__restrict__ I, int
         const int cnt = (int)min((long)CK, p1 - x0);
         stage_phi<L, E>(tm, I, a, j, x0, cnt, MODE != P_PRODUCT,
                         (MODE == P_UPDATE || MODE == P_CHECK) ? log_u : nullptr);
-        // forward states of the block
+        // forward states of the block: read back (W::SA) or recomputed from the checkpoint
         E F[CK][RG];
+        if constexpr (W::SA) {
 #pragma unroll
-        for (int i = 0; i < RG; ++i) A[i] = gld_e(&tm.ck[b * D + i * W::TL + t]);
+            for (int s = 0; s < CK; ++s)
 #pragma unroll
-        for (int s = 0; s < CK; ++s) {
-            if (s < cnt) wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt, 1), t);
+                for (int i = 0; i < RG; ++i)
+                    F[s][i] = gld_e(&tm.ck[(x0 - p0 + min(s, cnt - 1)) * D + i * W::TL + t]);
+        } else {
 #pragma unroll
-            for (int i = 0; i < RG; ++i) F[s][i] = A[i];
+            for (int i = 0; i < RG; ++i) A[i] = gld_e(&tm.ck[b * D + i * W::TL + t]);
+#pragma unroll
+            for (int s = 0; s < CK; ++s) {
+                if (s < cnt) wstep<L, E, false>(A, tm.ph + s * n, wconst_row<L, E>(tm, grid, s, pt, 1), t);
+#pragma unroll
+                for (int i = 0; i < RG; ++i) F[s][i] = A[i];
+            }
         }
 #pragma unroll
         for (int s = CK - 1; s >= 0; --s) {
