@@ -64,9 +64,9 @@ __device__ void fast_consts(FastConst<M, L, V> &C, double hoe, int tid, int nthr
 __device__ __forceinline__ double block_sum(double x, double *red, int lane, int wave, int nw)
 {
     x = wave_sum(x);
-    __syncthreads();
+    lds_barrier();
     if (lane == 0) red[wave] = x;
-    __syncthreads();
+    lds_barrier();
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += red[w];
     return s;
@@ -78,7 +78,7 @@ __device__ __forceinline__ bool block_any(bool p, int *fl, int &phase, int lane,
 {
     const bool w = __ballot(p) != 0;
     if (lane == 0) fl[phase * FAST_MAXW + wave] = w ? 1 : 0;
-    __syncthreads();
+    lds_barrier();
     int r = 0;
     for (int i = 0; i < nw; ++i) r |= fl[phase * FAST_MAXW + i];
     phase ^= 1;
@@ -183,7 +183,7 @@ __device__ __forceinline__ void bscan(const M (&pm)[L][V], const int (&pe)[L], M
             const XF<M> wagg = xf_of(rlane_xb(incl, FWD ? WAVE - 1 : 0));
             if (lane == 0) xw[(half * FAST_MAXW + sw) * D + S] = wagg;
         }
-        __syncthreads();
+        lds_barrier();
         // wavefronts: carry into this wavefront from the earlier ones, then per lane
 #pragma unroll
         for (int S = 1; S < D; ++S) {
@@ -358,7 +358,7 @@ __device__ __forceinline__ int load_row(const double *__restrict__ a, long N, lo
 {
     double x[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) x[v] = (p0 + v < N) ? a[p0 + v] : -INFINITY;
+    for (int v = 0; v < V; ++v) x[v] = (p0 + v < N) ? gld(&a[p0 + v]) : -INFINITY;
     return bf_row<M, V>(x, m, e);
 }
 
@@ -431,17 +431,26 @@ __device__ __forceinline__ void fast_sweeps(const Inst *__restrict__ I, const Pt
             double an[V];
             double *__restrict__ aj = pa + (long)j * N + p0;
             const double *__restrict__ luj = plu + (long)j * N + p0;
+            // the update's operands are loaded before the scans (global loads: they land
+            // while the scans run, and LDS reads never wait for them)
+            double luv[V], aov[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const bool in = p0 + v < N;
+                luv[v] = in ? gld(&luj[v]) : -INFINITY;
+                aov[v] = in ? gld(&aj[v]) : 0.0;
+            }
             bproduct<L, V, M>(pm, pe, sh.c, sh.xw, sh.fm, sh.fe, tid, FastShared<L, V, M>::T, lane, wave, nw,
                               [&](int v, double lj) {
                                   const bool in = p0 + v < N;
-                                  const double lu = in ? luj[v] : -INFINITY;
+                                  const double lu = luv[v];
                                   double x = lu - lj;
                                   if (lu > -INFINITY) {
-                                      if (j < L - 1) est += est_term(lu, aj[v] - x);
+                                      if (j < L - 1) est += est_term(lu, aov[v] - x);
                                   } else {
                                       x = -INFINITY;
                                   }
-                                  if (in) aj[v] = x;
+                                  if (in) gst(&aj[v], x);
                                   an[v] = x;
                               });
             // new row j into the last slot, then rotate the ring by one
@@ -535,11 +544,18 @@ __device__ __forceinline__ void fast_check(const Inst *__restrict__ I, const Ptr
             wide = true;
             break;
         }
+        double luv[V], aov[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const bool in = p0 + v < N;
+            luv[v] = in ? gld(&plu[(long)j * N + p0 + v]) : -INFINITY;
+            aov[v] = in ? gld(&pa[(long)j * N + p0 + v]) : 0.0;
+        }
         bproduct<L, V, double>(pm, pe, sh.c, sh.xw, sh.fm, sh.fe, tid, FastShared<L, V, double>::T, lane, wave, nw,
                                [&](int v, double lj) {
                                    if (p0 + v < N) {
-                                       const double lu = plu[(long)j * N + p0 + v];
-                                       if (lu > -INFINITY) r += fabs(exp(pa[(long)j * N + p0 + v] + lj) - exp(lu));
+                                       const double lu = luv[v];
+                                       if (lu > -INFINITY) r += fabs(exp(aov[v] + lj) - exp(lu));
                                    }
                                });
         // rotate the ring by one (the rows do not change)

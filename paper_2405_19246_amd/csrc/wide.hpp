@@ -67,40 +67,6 @@ struct WL {
     static constexpr bool SA = wide_store_all(L, EWords<E>::n);  // forward states of every position kept
 };
 
-// ---- global memory through global-address-space pointers -------------------------
-// A load or store through a generic pointer compiles to a flat instruction, which
-// also counts against the LDS wait counter: every LDS read after it would wait for
-// the global access to land.  The walks' global accesses go through these.
-template <typename T>
-__device__ __forceinline__ T gld(const T *p)
-{
-    return *(const __attribute__((address_space(1))) T *)p;
-}
-template <typename T>
-__device__ __forceinline__ void gst(T *p, T v)
-{
-    *(__attribute__((address_space(1))) T *)p = v;
-}
-// element kinds (XF, DXF) word by word
-template <typename E>
-__device__ __forceinline__ E gld_e(const E *p)
-{
-    E v;
-    int *d = reinterpret_cast<int *>(&v);
-    const __attribute__((address_space(1))) int *q = (const __attribute__((address_space(1))) int *)p;
-#pragma unroll
-    for (int w = 0; w < (int)(sizeof(E) / 4); ++w) d[w] = q[w];
-    return v;
-}
-template <typename E>
-__device__ __forceinline__ void gst_e(E *p, E v)
-{
-    const int *d = reinterpret_cast<const int *>(&v);
-    __attribute__((address_space(1))) int *q = (__attribute__((address_space(1))) int *)p;
-#pragma unroll
-    for (int w = 0; w < (int)(sizeof(E) / 4); ++w) q[w] = d[w];
-}
-
 // ---- lane moves inside a team ---------------------------------------------------
 // UP = false: the value of lane t - 2^B; UP = true: of lane t + 2^B.  Only lanes
 // whose source lies in the same team use the result.
@@ -168,13 +134,6 @@ __device__ __forceinline__ void team_sync_global()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Workgroup barrier ordering LDS only (as team_sync, for a whole workgroup).
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // Per-lane constants of one walk: g(level) for the levels this lane's registers
 // can hold.  Forward state S_i = i TL + t has level m + |t| + |i|; the

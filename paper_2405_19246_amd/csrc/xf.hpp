@@ -383,4 +383,46 @@ struct ET<DXF> {
     static __device__ __forceinline__ El rl(El a, int l) { return {P::rl(a.v, l), P::rl(a.w, l)}; }
 };
 
+// ---- global memory through global-address-space pointers -------------------------
+// A load or store through a generic pointer compiles to a flat instruction, which
+// also counts against the LDS wait counter: every LDS read after it would wait for
+// the global access to land.  The walks' global accesses go through these.
+template <typename T>
+__device__ __forceinline__ T gld(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T *p, T v)
+{
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+// element kinds (XF, DXF) word by word
+template <typename E>
+__device__ __forceinline__ E gld_e(const E *p)
+{
+    E v;
+    int *d = reinterpret_cast<int *>(&v);
+    const __attribute__((address_space(1))) int *q = (const __attribute__((address_space(1))) int *)p;
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(E) / 4); ++w) d[w] = q[w];
+    return v;
+}
+template <typename E>
+__device__ __forceinline__ void gst_e(E *p, E v)
+{
+    const int *d = reinterpret_cast<const int *>(&v);
+    __attribute__((address_space(1))) int *q = (__attribute__((address_space(1))) int *)p;
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(E) / 4); ++w) q[w] = d[w];
+}
+
+// Workgroup barrier ordering LDS only (as team_sync, for a whole workgroup).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 }  // namespace mmot
