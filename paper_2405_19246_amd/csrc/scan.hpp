@@ -339,7 +339,7 @@ __device__ __forceinline__ const Disc<M> *upd_disc(const Inst *I)
 template <typename E>
 __device__ __forceinline__ void store_elem(void *base, long idx, int lane_ok, E x)
 {
-    if (lane_ok) reinterpret_cast<E *>(base)[idx] = x;
+    if (lane_ok) gst_e(reinterpret_cast<E *>(base) + idx, x);
 }
 
 // Wave-wide FP64 sum, the same value in every lane.  (A butterfly leaves each
@@ -386,6 +386,24 @@ __device__ __forceinline__ double finish_lj(double lj, int j, long N, long p, do
     }
 }
 
+// finish_lj with a_j(p) (ao) and log u_j(p) (lu) already loaded; stores through
+// global-address-space pointers.
+template <int MODE>
+__device__ __forceinline__ double finish_pre(double lj, double lu, double ao, int j, long N, long p,
+                                             double *__restrict__ a, double *__restrict__ out)
+{
+    if constexpr (MODE == P_PRODUCT) {
+        gst(&out[p], lj);
+        return 0.0;
+    } else if constexpr (MODE == P_UPDATE) {
+        const double an = lu > -INFINITY ? lu - lj : -INFINITY;
+        gst(&a[(long)j * N + p], an);
+        return lu > -INFINITY ? exp(lu) * fabs(expm1(ao - an)) : 0.0;
+    } else {
+        return fabs(exp(ao + lj) - exp(lu));
+    }
+}
+
 // One marginal pass over an instance on one wavefront.
 //   P_PRODUCT:   out[y] = log J_j(y)
 //   P_UPDATE:    a_j(y) = log u_j(y) - log J_j(y)           (Gauss-Seidel step);
@@ -423,12 +441,13 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
     // chunk whose rows fit them (wavefront-uniform choice), the extended-range
     // scans otherwise; both keep the chunk carries in extended range.
     constexpr bool BF = std::is_same<E, XF<float>>::value && (MODE == P_PRODUCT || MODE == P_UPDATE);
+    constexpr bool PRE = std::is_same<M, double>::value;
     auto load_a = [&](long c, double(&av)[n][V]) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const long p = c * CH + (long)lane * V + v;
 #pragma unroll
-            for (int r = 0; r < n; ++r) av[r][v] = (p < N) ? a[(long)items[r] * N + p] : -INFINITY;
+            for (int r = 0; r < n; ++r) av[r][v] = (p < N) ? gld(&a[(long)items[r] * N + p]) : -INFINITY;
         }
     };
     auto to_phi = [&](const double(&av)[n][V], XF<M>(&phi)[n][V]) {
@@ -485,9 +504,23 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
     for (long c = C - 1; c >= 0; --c) {
         double av[n][V];
         load_a(c, av);
+        // the epilogue's operands (a_j, log u_j at the chunk's positions): with FP64
+        // mantissas loaded before the scans, so that they have landed when the
+        // combine needs them; with FP32 ones, whose scans hold more state per
+        // register budget, at the combine (held across the scans they spill)
+        double ajc[V], luc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const long p = c * CH + (long)lane * V + v;
+            const bool in = p < N;
+            if constexpr (PRE) {
+                ajc[v] = (MODE != P_PRODUCT && in) ? gld(&a[(long)j * N + p]) : 0.0;
+                luc[v] = ((MODE == P_UPDATE || MODE == P_CHECK) && in) ? gld(&log_u[(long)j * N + p]) : 0.0;
+            }
+        }
         if (C > 1) {
 #pragma unroll
-            for (int S = 1; S < D; ++S) carryF[S] = reinterpret_cast<const E *>(scratch)[c * (D - 1) + (S - 1)];
+            for (int S = 1; S < D; ++S) carryF[S] = gld_e(reinterpret_cast<const E *>(scratch) + c * (D - 1) + (S - 1));
         }
         if constexpr (BF) {
             float pm[n][V];
@@ -503,7 +536,8 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const long p = c * CH + (long)lane * V + v;
-                    if (p < N) acc += finish_lj<MODE>(ljv[v], j, N, p, a, log_u, out);
+                    if (p < N) acc += PRE ? finish_pre<MODE>(ljv[v], luc[v], ajc[v], j, N, p, a, out)
+                                          : finish_lj<MODE>(ljv[v], j, N, p, a, log_u, out);
                 }
                 continue;
             }
@@ -534,10 +568,11 @@ __device__ double marginal_pass(const Inst *__restrict__ I, const Disc<typename 
             }
             if (p < N) {
                 if constexpr (MODE == P_OBJECTIVE) {
-                    const XF<double> ph = xfrom_log<double>(a[(long)j * N + p]);
+                    const XF<double> ph = xfrom_log<double>(ajc[v]);
                     accx = xadd(accx, xmul(ph, J.w));
                 } else {
-                    acc += finish_lj<MODE>(xto_log(J), j, N, p, a, log_u, out);
+                    acc += PRE ? finish_pre<MODE>(xto_log(J), luc[v], ajc[v], j, N, p, a, out)
+                               : finish_lj<MODE>(xto_log(J), j, N, p, a, log_u, out);
                 }
             }
         }
