@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -453,6 +454,23 @@ struct BatchArena {
     BatchBuffers bb = {};
     char *scratch = nullptr;
     size_t cap_inst = 0, cap_scratch = 0;
+    Inst *hI = nullptr;  // pinned host descriptors (the source of the descriptor upload)
+    size_t cap_host = 0;
+
+    int reserve_host(size_t count)
+    {
+        if (count <= cap_host) return MMOT_OK;
+        if (hI) (void)hipHostFree(hI);
+        hI = nullptr;
+        cap_host = 0;
+        const size_t c = std::max<size_t>(count, 64);
+        if (hipHostMalloc((void **)&hI, c * sizeof(Inst), hipHostMallocDefault) != hipSuccess) {
+            hI = nullptr;
+            return fail(MMOT_ERR_NOMEM, "pinned batch descriptor allocation failed");
+        }
+        cap_host = c;
+        return MMOT_OK;
+    }
 
     int reserve(size_t count, size_t scratch_total)
     {
@@ -899,7 +917,6 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
         if (rc) return rc;
         if (o->flags & MMOT_FLAG_JACOBI) return fail(MMOT_ERR_UNSUPPORTED, "MMOT_FLAG_JACOBI is a plan option");
         if (count == 0) return MMOT_OK;
-        std::vector<Inst> hI(count);
         std::vector<Ptrs> hP(count);
         size_t off = 0;
         std::vector<size_t> offs(count);
@@ -908,15 +925,38 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
             rc = check_shape(inst[i].l, inst[i].N, grid ? 1.0 : inst[i].h, inst[i].eps);
             if (rc) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
             if (!inst[i].log_u || !inst[i].log_phi) return fail(MMOT_ERR_INVALID, "instance " + std::to_string(i) + ": NULL buffer");
-            // non-uniform grid: tiled kernels, no factor h on the objective (as mmot_plan)
-            hI[i] = make_inst(inst[i].l, inst[i].N, grid ? 1.0 : inst[i].h, inst[i].eps);
-            hI[i].x = inst[i].x;
             offs[i] = off;
             off += scratch_bytes(inst[i].l, inst[i].N, precision, (o->flags & MMOT_FLAG_TILES) || grid ? F_TILES : 0);
         }
         std::lock_guard<std::mutex> lk(g_batch.mu);
         rc = g_batch.reserve((size_t)count, std::max<size_t>(off, 256));
         if (rc) return rc;
+        rc = g_batch.reserve_host((size_t)count);
+        if (rc) return rc;
+        // Descriptors, written into pinned memory.  The discount tables depend on l
+        // and h / eps only: they are computed once per distinct pair and copied.
+        Inst *hI = g_batch.hI;
+        std::map<std::pair<int, uint64_t>, int> owner;
+        for (int i = 0; i < count; ++i) {
+            // non-uniform grid: tiled kernels, no factor h on the objective (as mmot_plan)
+            const double he = inst[i].x ? 1.0 : inst[i].h;
+            const double hoe = he / inst[i].eps;
+            uint64_t bits;
+            std::memcpy(&bits, &hoe, sizeof bits);
+            const auto key = std::make_pair((int)inst[i].l, bits);
+            const auto it = owner.find(key);
+            if (it == owner.end()) {
+                hI[i] = make_inst(inst[i].l, inst[i].N, he, inst[i].eps);
+                owner.emplace(key, i);
+            } else {
+                std::memcpy(&hI[i], &hI[it->second], sizeof(Inst));
+                hI[i].N = inst[i].N;
+                hI[i].h = he;
+                hI[i].hoe = hoe;
+                hI[i].ieps = 1.0 / inst[i].eps;
+            }
+            hI[i].x = inst[i].x;
+        }
         for (int i = 0; i < count; ++i)
             hP[i] = {inst[i].log_u, inst[i].log_phi, nullptr, g_batch.scratch + offs[i], 0, 0,
                      ((o->flags & MMOT_FLAG_WARM_START) ? F_WARM : 0) | (inst[i].x ? F_TILES : 0), 0};
@@ -927,8 +967,13 @@ extern "C" int mmot_solve_batch(const mmot_instance *inst, int32_t count, int32_
                       FAST_WARMUP_SWEEPS};
         BatchBuffers bb = g_batch.bb;
         std::vector<Result> hR(count);
-        rc = batch_launch(hI.data(), hP.data(), count, precision, ro, (hipStream_t)hip_stream, hR.data(), &bb, true);
-        if (rc) return rc;
+        rc = batch_launch(hI, hP.data(), count, precision, ro, (hipStream_t)hip_stream, hR.data(), &bb, true);
+        if (rc) {
+            // the descriptor upload reads the pinned buffer asynchronously: let it
+            // finish before a later call rewrites the buffer
+            (void)hipStreamSynchronize((hipStream_t)hip_stream);
+            return rc;
+        }
         int worst = MMOT_OK;
         for (int i = 0; i < count; ++i) {
             std::memcpy(&res[i], &hR[i], sizeof(Result));
