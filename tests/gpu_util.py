@@ -4,6 +4,16 @@ import sys
 import numpy as np
 
 
+# Bar for one FP32-scan product or one FP32 sweep against the FP64 oracle (relative
+# error of J, or of the potentials).  The products round in FP32 (unit roundoff
+# 2^-24 = 6.0e-8) through a few dozen operations whose errors decay with the
+# discount factors; measured: 1.6e-7 .. 7.7e-7 over every FP32 product and
+# one-sweep test (l = 3..10, uniform and graded grids, one wavefront, teams and
+# tiles).  The bar is 4e-6, about 67 roundings: a five-fold margin over the
+# largest error seen, so a regression of ten times fails.
+FP32_TOL = 4e-6
+
+
 def say(msg: str) -> None:
     """Name the case before a GPU step, flushed, so a failing run shows where it was."""
     print("[case] " + msg, flush=True)

@@ -3,7 +3,7 @@ against the extended-range solver (MMOT_FLAG_NO_FAST)."""
 import numpy as np
 import pytest
 
-from gpu_util import potentials_err, say, to_dev
+from gpu_util import FP32_TOL, potentials_err, say, to_dev
 from oracle import fastcheck
 from paper_2405_19246_amd import inputs
 
@@ -84,7 +84,7 @@ def test_fast_fp32_one_sweep_from_oracle_iterates():
         ref = fastcheck.sinkhorn(u, h, eps, itmax=1, check_every=10**9, log_phi0=a)["log_phi"]
         e = potentials_err(t.cpu().numpy(), ref)
         worst = max(worst, e)
-        assert e < 2e-5, (k, e)
+        assert e < FP32_TOL, (k, e)
     print("fast fp32 one sweep: worst potentials error %.3e" % worst)
 
 

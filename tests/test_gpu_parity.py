@@ -3,13 +3,13 @@
 Tolerances.  FP64: 1e-12 relative (products pointwise, potentials relative to
 max(1, |a|), objective scalar) -- the bar the paper's own fast-vs-dense plan
 differences of ~1e-16 show is reachable (Table 1, Sec. 5.1).  FP32 scans: the
-error is measured and printed; the test bounds it by 2e-5 relative for a single
+error is measured and printed; the test bounds it by FP32_TOL (4e-6) relative for a single
 product, and by the FP64 marginal-error certificate for solves.
 """
 import numpy as np
 import pytest
 
-from gpu_util import dev, log_rel_err, potentials_err, say, to_dev
+from gpu_util import FP32_TOL, dev, log_rel_err, potentials_err, say, to_dev
 from oracle import dense, fastcheck
 from paper_2405_19246_amd import inputs
 
@@ -75,7 +75,7 @@ def test_product_fp32_error_is_small(l, N):
         got = plan.marginal_product(j, to_dev(a)).cpu().numpy()
         worst = max(worst, log_rel_err(got, fastcheck.marginal_product_log(a, j, h, eps)))
     print("fp32 product l=%d N=%d: max relative error %.3e" % (l, N, worst))
-    assert worst < 2e-5
+    assert worst < FP32_TOL
 
 
 def test_extreme_potentials_stay_finite():
@@ -99,7 +99,7 @@ def test_extreme_potentials_stay_finite():
             got = plan.marginal_product(j, to_dev(a)).cpu().numpy()
             worst = max(worst, log_rel_err(got, refs[j], mag_ulps=16))
         print("extreme product prec=%d: relative error beyond 16 ulps of |log J|: %.3e" % (prec, worst))
-        assert worst < (FP64_TOL if prec == mmot.FP64 else 2e-5)
+        assert worst < (FP64_TOL if prec == mmot.FP64 else FP32_TOL)
 
 
 def test_solve_fp64_plain_method_500_sweeps():

@@ -13,7 +13,7 @@ objective); FP32 solves certified by the oracle's FP64 marginal errors.
 import numpy as np
 import pytest
 
-from gpu_util import log_rel_err, potentials_err, say, to_dev
+from gpu_util import FP32_TOL, log_rel_err, potentials_err, say, to_dev
 from oracle import fastcheck
 from paper_2405_19246_amd import inputs
 
@@ -63,7 +63,7 @@ def test_tiled_product_fp32_error_is_small(l, N):
         got = plan.marginal_product(j, to_dev(a)).cpu().numpy()
         worst = max(worst, log_rel_err(got, fastcheck.marginal_product_log(a, j, h, eps)))
     print("tiled fp32 product l=%d N=%d: max relative error %.3e" % (l, N, worst))
-    assert worst < 2e-5
+    assert worst < FP32_TOL
 
 
 @pytest.mark.parametrize("l,N", [(3, 70), (4, 50), (6, 40), (8, 30), (10, 19)])

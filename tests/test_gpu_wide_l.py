@@ -14,7 +14,7 @@ marginal errors of the returned potentials.
 import numpy as np
 import pytest
 
-from gpu_util import log_rel_err, potentials_err, say, to_dev
+from gpu_util import FP32_TOL, log_rel_err, potentials_err, say, to_dev
 from oracle import dense, fastcheck
 from paper_2405_19246_amd import inputs
 
@@ -98,7 +98,7 @@ def test_product_fp32_wide_l_error_is_small(l, N):
         got = plan.marginal_product(j, to_dev(a)).cpu().numpy()
         worst = max(worst, log_rel_err(got, fastcheck.marginal_product_log(a, j, h, eps)))
     print("fp32 product l=%d N=%d: max relative error %.3e" % (l, N, worst))
-    assert worst < 2e-5
+    assert worst < FP32_TOL
 
 
 @pytest.mark.parametrize("l,N", [(7, 40), (8, 24), (9, 20), (10, 11)])
