@@ -43,7 +43,7 @@ extern "C" {
 #define MMOT_ERR_NOMEM (-2)       /* device or host allocation failed */
 #define MMOT_ERR_NUMERIC (-3)     /* a NaN or infinity appeared in a potential, the residual or the objective */
 #define MMOT_NOT_CONVERGED (-4)   /* itr_max reached with residual > tol; outputs are still written */
-#define MMOT_ERR_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define MMOT_ERR_UNSUPPORTED (-5) /* valid request the library does not implement */
 #define MMOT_ERR_HIP (-6)         /* a HIP runtime call failed (message names it) */
 #define MMOT_ERR_STATE (-7)       /* server stopped, unknown ticket, or call out of order */
 #define MMOT_ERR_INTERNAL (-8)    /* unexpected failure inside the library (host resources; message names it) */

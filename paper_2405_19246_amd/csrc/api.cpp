@@ -51,7 +51,7 @@ int check_shape(int l, int64_t N, double h, double eps)
 {
     if (l < 2 || l > MMOT_MAX_L) return fail(MMOT_ERR_INVALID, "l must be in [2, " + std::to_string(MMOT_MAX_L) + "]");
     if (l > MMOT_BUILD_MAXL)
-        return fail(MMOT_ERR_UNSUPPORTED, "this build solves l <= " + std::to_string(MMOT_BUILD_MAXL));
+        return fail(MMOT_ERR_UNSUPPORTED, "the library solves l <= " + std::to_string(MMOT_BUILD_MAXL));
     if (N < 1) return fail(MMOT_ERR_INVALID, "N must be >= 1");
     if (N > (int64_t(1) << 31) / l) return fail(MMOT_ERR_INVALID, "l * N too large");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(MMOT_ERR_INVALID, "eps must be finite and > 0");
