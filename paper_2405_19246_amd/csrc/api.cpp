@@ -742,30 +742,55 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
         // a round of o.warmup sweeps for every instance; from the estimate's decay
         // over its second half each instance's remaining sweeps are predicted,
         // and the later rounds take the group in that order, longest first, so
-        // that the slowest solves do not start last.  Iterates are unchanged.
+        // that the slowest solves do not start last (reordered on the device up
+        // to FAST_ORDER_MAX instances, else by the host).  Rounds are pairs of a
+        // sweep and a check launch; for such groups FAST_PAIRS of them are
+        // enqueued back to back before the host reads the states (a solve whose
+        // check fails goes on in the next pair).  Iterates are unchanged.
         bool warm[MAXL + 1];
         for (int l = 0; l <= MAXL; ++l)
             warm[l] = o.warmup >= 2 && o.tol >= 0.0 && (int)group[l].size() > FAST_RESIDENT;
         for (;;) {
             bool any = false;
+            int pairs_max = 0;
             for (int l = 2; l <= MAXL; ++l) {
                 if (!sweeping[l]) continue;
                 any = true;
                 const int n = (int)group[l].size();
                 const int cap = 256 * 8;  // persistent workgroups: a few per CU
-                RunOpts so = o;
-                so.budget = warm[l] ? o.warmup : 0;
-                HIPCHK(tbegin(0));
-                HIPCHK(launch_fast(0, l, precision, bb->dI, bb->dP, bb->dorder + goff[l], n, so, bb->dT, bb->dticket,
-                                   std::min(n, cap), fast_waves(l, gmaxN[l], 0, precision), s));
-                HIPCHK(tend());
-                HIPCHK(tbegin(1));
-                HIPCHK(launch_fast(1, l, precision, bb->dI, bb->dP, bb->dorder + goff[l], n, o, bb->dT, bb->dticket,
-                                   std::min(n, cap), fast_waves(l, gmaxN[l], 1, precision), s));
-                HIPCHK(tend());
+                auto pair = [&](int budget) -> hipError_t {
+                    RunOpts so = o;
+                    so.budget = budget;
+                    hipError_t e = tbegin(0);
+                    if (e == hipSuccess)
+                        e = launch_fast(0, l, precision, bb->dI, bb->dP, bb->dorder + goff[l], n, so, bb->dT,
+                                        bb->dticket, std::min(n, cap), fast_waves(l, gmaxN[l], 0, precision), s);
+                    if (e == hipSuccess) e = tend();
+                    if (e == hipSuccess) e = tbegin(1);
+                    if (e == hipSuccess)
+                        e = launch_fast(1, l, precision, bb->dI, bb->dP, bb->dorder + goff[l], n, o, bb->dT,
+                                        bb->dticket, std::min(n, cap), fast_waves(l, gmaxN[l], 1, precision), s);
+                    if (e == hipSuccess) e = tend();
+                    return e;
+                };
+                int pairs = 0;
+                if (warm[l]) {
+                    HIPCHK(pair(o.warmup));
+                    ++pairs;
+                    if (n <= FAST_ORDER_MAX) {
+                        HIPCHK(launch_fast_order(bb->dT, bb->dorder + goff[l], n, o.tol, o.warmup, s));
+                        warm[l] = false;
+                        for (int k = 0; k < FAST_PAIRS; ++k, ++pairs) HIPCHK(pair(0));
+                    }
+                } else {
+                    // after a reordering (large groups) several pairs, else one
+                    const int np = (int)group[l].size() > FAST_RESIDENT ? FAST_PAIRS : 1;
+                    for (int k = 0; k < np; ++k, ++pairs) HIPCHK(pair(0));
+                }
+                pairs_max = std::max(pairs_max, pairs);
             }
             if (!any) break;
-            ++rounds;
+            rounds += pairs_max;
             HIPCHK(hipMemcpyAsync(hT.data(), bb->dT, sizeof(Track) * count, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             for (int l = 2; l <= MAXL; ++l) {

@@ -160,6 +160,13 @@ constexpr int fast_waves_per_eu(int precision) { return precision == 1 ? 3 : 1; 
 // longest predicted solve first.
 constexpr int FAST_RESIDENT = 768;
 constexpr int FAST_WARMUP_SWEEPS = 256;
+// Groups up to this size are reordered after the warm-up on the device (one
+// workgroup sorts them in LDS); larger ones by the host.
+constexpr int FAST_ORDER_MAX = 4096;
+// Pairs of sweep and check launches enqueued back to back after the reordering
+// before the host reads the solves' states (a pair with nothing left to do costs
+// two near-empty launches).
+constexpr int FAST_PAIRS = 4;
 
 // Block floating point holds while the values one thread keeps span at most
 // this many bits: rows of l - 1 marginals (row_spread bits each), v positions

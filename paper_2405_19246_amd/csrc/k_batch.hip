@@ -125,6 +125,78 @@ __global__ __launch_bounds__(256) void k_objective_batch(const Inst *I, const Pt
 }
 
 
+// Predicted sweeps a solve still needs after a warm-up round of `warmup` sweeps:
+// the estimate fell from est_mid to est over the round's second half; at the same
+// geometric rate it reaches tol * f after log(est / (tol f)) / rate more sweeps.
+// Solves not sweeping come last (-1); an estimate that did not fall ranks first.
+__device__ __forceinline__ double remaining_sweeps_dev(const Track &T, double tol, int warmup)
+{
+    if (T.state != TS_SWEEP) return -1.0;
+    const double tgt = tol * T.f;
+    if (!(T.est > tgt)) return 0.0;
+    if (!(T.est_mid > T.est) || !(T.est > 0.0)) return INFINITY;
+    const double rate = log(T.est_mid / T.est) / (double)(warmup / 2);
+    return log(T.est / fmax(tgt, 1e-300)) / rate;
+}
+
+// One workgroup: bitonic sort of (predicted remaining sweeps, position) in LDS,
+// longest first and positions ascending among equal keys (the host's stable
+// order), then list rewritten in that order.
+__global__ __launch_bounds__(1024) void k_fast_order(const Track *T, int *list, int n, double tol, int warmup)
+{
+    __shared__ double key[FAST_ORDER_MAX];
+    __shared__ int pos[FAST_ORDER_MAX];
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        const double r = i < n ? remaining_sweeps_dev(T[list[i]], tol, warmup) : -INFINITY;
+        key[i] = r == r ? r : INFINITY;
+        pos[i] = i;
+    }
+    __syncthreads();
+    // a comes after b: smaller key, or the same key and a later position
+    auto after = [&](int a, int b) { return key[a] < key[b] || (key[a] == key[b] && pos[a] > pos[b]); };
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int x = i ^ j;
+                if (x > i) {
+                    const bool up = (i & k) == 0;
+                    if (up ? after(i, x) : after(x, i)) {
+                        const double tk = key[i];
+                        key[i] = key[x];
+                        key[x] = tk;
+                        const int tp = pos[i];
+                        pos[i] = pos[x];
+                        pos[x] = tp;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // every read of the old order before any write (n <= 4 * blockDim.x)
+    int v[FAST_ORDER_MAX / 1024];
+#pragma unroll
+    for (int r = 0; r < FAST_ORDER_MAX / 1024; ++r) {
+        const int i = threadIdx.x + r * 1024;
+        v[r] = i < n ? list[pos[i]] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < FAST_ORDER_MAX / 1024; ++r) {
+        const int i = threadIdx.x + r * 1024;
+        if (i < n) list[i] = v[r];
+    }
+}
+
+hipError_t launch_fast_order(const Track *dT, int *list, int n, double tol, int warmup, hipStream_t s)
+{
+    if (n < 1 || n > FAST_ORDER_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fast_order, dim3(1), dim3(1024), 0, s, dT, list, n, tol, warmup);
+    return hipGetLastError();
+}
+
 hipError_t launch_solve_batch(int precision, const Inst *dI, const Ptrs *dP, const int *dorder, int count,
                               const RunOpts &o, Result *dR, int *dticket, int blocks, hipStream_t s)
 {

@@ -77,6 +77,10 @@ hipError_t launch_check_marginals(const Inst *dI, const Ptrs *dP, int count, int
 // and a constant fill (potentials phi = 1/N).
 hipError_t launch_jacobi_update(double *a, const double *log_u, const double *logJ, long n, int l, hipStream_t s);
 hipError_t launch_fill(double *a, long n, double v, hipStream_t s);
+// Reorders list[0..n) (n <= FAST_ORDER_MAX) by the sweeps each solve is predicted to
+// still need after a warm-up of `warmup` sweeps, longest first (ties keep their
+// order); one workgroup, so the batch host needs no copy of the states for it.
+hipError_t launch_fast_order(const Track *dT, int *list, int n, double tol, int warmup, hipStream_t s);
 
 // phi = 1/N for the listed instances that do not start warm.
 hipError_t launch_tile_init(const Inst *dI, const Ptrs *dP, const int *dlist, int count, const RunOpts &o,

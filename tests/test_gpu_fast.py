@@ -178,3 +178,36 @@ def test_fast_longest_first_reordering_keeps_iterates():
         assert x["iters"] == y["iters"]
         assert x["marg_err"] == y["marg_err"] and x["W"] == y["W"]
         assert torch.equal(da["log_phi"], db["log_phi"])
+
+
+def test_fast_reordering_on_host_beyond_device_sort_keeps_iterates():
+    # Groups of up to 4096 instances are reordered after the warm-up by one
+    # workgroup on the device; larger ones by the host.  Both orders change no
+    # iterate: a group of 4200 (host order) and the same instances in two
+    # groups of 2100 (device order) give bitwise the same results.
+    import torch
+    mmot = _mmot()
+    n = 4200
+
+    def make():
+        out = []
+        for s in range(n):
+            u = inputs.marginals(3, 64, K=3, master_seed=41, instance=s)
+            out.append(dict(l=3, N=64, h=inputs.grid_step(64), eps=0.02 if s % 5 else 0.008, u=u))
+        return _dev(out)
+
+    a, b = make(), make()
+    say("batch of %d, reordered by the host" % n)
+    ra = mmot.solve_batch(a, precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
+    say("same instances in two batches of %d, reordered on the device" % (n // 2))
+    rb = mmot.solve_batch(b[: n // 2], precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
+    rb += mmot.solve_batch(b[n // 2:], precision=mmot.FP32, tol=1e-6, itr_max=30000, check_every=0)
+    torch.cuda.synchronize()
+    its = np.array([x["iters"] for x in ra])
+    print("sweeps: min %d median %d max %d" % (its.min(), np.median(its), its.max()))
+    assert (its > 256).mean() > 0.3
+    for da, db, x, y in zip(a, b, ra, rb):
+        assert x["status"] == y["status"] == 0
+        assert x["iters"] == y["iters"]
+        assert x["marg_err"] == y["marg_err"] and x["W"] == y["W"]
+        assert torch.equal(da["log_phi"], db["log_phi"])
