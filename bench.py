@@ -305,6 +305,29 @@ def next_rows(dev):
     return {"twod_eps0.1_100_sweeps": twod, "grid_l4_n1000_eps0.01": grid, "jacobi_l4_n300_eps0.05": jac}
 
 
+def dense_comparator(dev, sweeps: int = 10):
+    """The dense O(N^l) Sinkhorn on the device against the O(N) scans, both FP64, one instance of
+    l = 4, N = 100, eps = 1e-2 (the headline shape at N = 100), the same sweeps from the same start."""
+    import torch
+    from paper_2405_19246_amd import inputs, mmot
+    l, N, eps = 4, 100, 0.01
+    u = inputs.marginals(l, N, K=3, master_seed=0, instance=0)
+    h = inputs.grid_step(N)
+    lu = torch.tensor(np.log(u), dtype=torch.float64, device=dev)
+    plan = mmot.Plan(l, N, h, eps, precision=mmot.FP64, tol=-1.0, itr_max=sweeps, check_every=0)
+    a0 = torch.full((l, N), -float(np.log(N)), dtype=torch.float64, device=dev)
+    ad, af = a0.clone(), a0.clone()
+    plan.dense_sinkhorn_iter(lu, a0.clone(), 1)
+    plan.sinkhorn_iter(lu, a0.clone(), 1, want_err=False)
+    torch.cuda.synchronize()
+    _, td = timed(lambda: plan.dense_sinkhorn_iter(lu, ad, sweeps))
+    _, tf = timed(lambda: plan.sinkhorn_iter(lu, af, sweeps, want_err=False))
+    diff = float(torch.max(torch.abs((ad - ad.mean()) - (af - af.mean()))).item())
+    return dict(l=l, N=N, eps=eps, sweeps=sweeps, dense_ms_per_sweep=td / sweeps * 1e3,
+                scans_ms_per_sweep=tf / sweeps * 1e3, scans_speedup=td / tf,
+                dense_units_per_s=l * N * sweeps / td, max_potential_difference=diff)
+
+
 def c4_batch(dev, count: int, itr_max: int):
     import torch
     from paper_2405_19246_amd import inputs, mmot
@@ -407,7 +430,7 @@ def main():
     ap.add_argument("--c4", type=int, default=0, metavar="COUNT",
                     help="also solve the first COUNT instances of the mixed batch configuration")
     ap.add_argument("--c4-itr-max", type=int, default=100000)
-    ap.add_argument("--only", choices=("plain", "l10", "serve_mixed", "ricker", "next_rows"),
+    ap.add_argument("--only", choices=("plain", "l10", "serve_mixed", "ricker", "next_rows", "dense"),
                     help="run only this extra leg and print its JSON (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 4 times (reference for HBM byte counters)")
@@ -443,7 +466,7 @@ def main():
     if args.only:
         leg = {"plain": lambda: plain_config(dev), "l10": lambda: l10_shape(dev, 3),
                "serve_mixed": lambda: serve_mixed(0.5, 8.0), "ricker": lambda: ricker(dev),
-               "next_rows": lambda: next_rows(dev)}[args.only]()
+               "next_rows": lambda: next_rows(dev), "dense": lambda: dense_comparator(dev)}[args.only]()
         print(json.dumps({"leg": args.only, **leg}), flush=True)
         return
     tol32, tol64 = 1e-6, 1e-8
@@ -524,6 +547,7 @@ def main():
         out["l10_n100000_eps0.001"] = l10_shape(dev, 3)
         out["ricker"] = ricker(dev)
         out["next_rows"] = next_rows(dev)
+        out["dense_comparator_l4_n100"] = dense_comparator(dev)
         (rx, tx) = timed(lambda: step(mmot.FP32, tol32, fast=False))
         out["one_wavefront_solver"] = dict(value=units_of(rx) / tx, seconds=tx,
                                            all_converged=all(r["status"] == 0 for r in rx),

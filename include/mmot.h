@@ -153,6 +153,24 @@ int mmot_plan_destroy(mmot_plan_t *plan);
 int mmot_marginal_product(const mmot_plan_t *plan, int32_t j, const double *log_phi, double *log_J);
 
 /*
+ * The same product from its definition, for comparison at small sizes: the sum
+ * over all N^(l-1) index tuples of the other marginals (Sec. 2, the
+ * tensor-vector product with the Gibbs kernel; Alg. 1 as written), O(N^l) work,
+ * FP64 log-sum-exp on the device, any plan precision.  Arguments as in
+ * mmot_marginal_product; the plan's grid (uniform or coordinates) sets the cost.
+ * MMOT_ERR_UNSUPPORTED unless l <= 6, (l + 1) N <= 6144 and N^(l-1) < 2^31.
+ */
+int mmot_dense_marginal_product(const mmot_plan_t *plan, int32_t j, const double *log_phi, double *log_J);
+
+/*
+ * n_sweeps Gauss-Seidel sweeps (Alg. 1 update lines) with the dense product
+ * above, FP64, no residual, from the potentials in log_phi (warm start).
+ * log_u: device [l][N]; log_phi: device [l][N], in/out.  Asynchronous on the
+ * plan's stream.  Same size limits as mmot_dense_marginal_product.
+ */
+int mmot_dense_sinkhorn_iter(const mmot_plan_t *plan, const double *log_u, double *log_phi, int64_t n_sweeps);
+
+/*
  * n_sweeps Gauss-Seidel sweeps (Alg. 1 loop body, l updates each) starting
  * from the potentials in log_phi, no early stop; warm start = resume.
  * log_u: device [l][N].  log_phi: device [l][N], in/out.

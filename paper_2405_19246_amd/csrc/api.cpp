@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "dense.hpp"
 #include "launch.hpp"
 #include "mmot.h"
 #include "serve.hpp"
@@ -89,6 +90,7 @@ struct mmot_plan {
     int ntile = 1, B = 0;
     double *dx = nullptr;  // non-uniform grid: device copy of the coordinates (tiled kernels)
     double *djac = nullptr;  // MMOT_FLAG_JACOBI: [l][N] products of one all-marginals sweep
+    double *ddense = nullptr;  // dense products: per-range partial sums (small problems only)
     TileInst hTI;
     mutable Ptrs hP;
     mutable std::vector<char> jobs_host;
@@ -151,6 +153,8 @@ int mmot_plan(const mmot_problem *p, const mmot_opts *o, void *hip_stream, mmot_
         if (e == hipSuccess) e = hipMalloc((void **)&pl->dI, sizeof(Inst));
         if (e == hipSuccess && (oo.flags & MMOT_FLAG_JACOBI))
             e = hipMalloc((void **)&pl->djac, sizeof(double) * (size_t)p->l * (size_t)p->N);
+        if (e == hipSuccess && dense_supported(p->l, p->N))
+            e = hipMalloc((void **)&pl->ddense, sizeof(double) * 2 * (size_t)p->N * (size_t)dense_ranges((int)p->N));
         if (e == hipSuccess) e = hipMalloc(&pl->scratch, std::max<size_t>(pl->scratch_size, 256));
         if (e == hipSuccess) e = hipMalloc((void **)&pl->dR, sizeof(Result));
         if (e == hipSuccess) e = hipMalloc((void **)&pl->dtmp, sizeof(double) * MAXL);
@@ -181,7 +185,8 @@ int mmot_plan_footprint(const mmot_plan_t *pl, size_t *device_bytes)
                         sizeof(Ptrs) + 3 * sizeof(int) + sizeof(Track) +
                         2 * sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N +
                         (pl->dx ? sizeof(double) * (size_t)pl->p.N : 0) +
-                        (pl->djac ? sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N : 0);
+                        (pl->djac ? sizeof(double) * (size_t)pl->p.l * (size_t)pl->p.N : 0) +
+                        (pl->ddense ? sizeof(double) * 2 * (size_t)pl->p.N * (size_t)dense_ranges((int)pl->p.N) : 0);
         return MMOT_OK;
     } catch (...) {
         return guard_fail();
@@ -199,6 +204,7 @@ int mmot_plan_destroy(mmot_plan_t *pl)
         if (pl->dtmp) (void)hipFree(pl->dtmp);
         if (pl->dx) (void)hipFree(pl->dx);
         if (pl->djac) (void)hipFree(pl->djac);
+        if (pl->ddense) (void)hipFree(pl->ddense);
         delete pl;
         return MMOT_OK;
     } catch (...) {
@@ -250,6 +256,37 @@ int mmot_marginal_product(const mmot_plan_t *pl, int32_t j, const double *log_ph
         if (pl->tiled) return plan_tile_pass(pl, P_PRODUCT, j, nullptr, log_phi, log_J);
         Ptrs P = {nullptr, const_cast<double *>(log_phi), log_J, pl->scratch, 0, 0, 0, 0};
         HIPCHK(launch_pass(pl->p.l, pl->p.precision, 0, pl->dI, P, j, nullptr, pl->s));
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
+    }
+}
+
+int mmot_dense_marginal_product(const mmot_plan_t *pl, int32_t j, const double *log_phi, double *log_J)
+{
+    try {
+        if (!pl || !log_phi || !log_J) return fail(MMOT_ERR_INVALID, "NULL argument");
+        if (j < 0 || j >= pl->p.l) return fail(MMOT_ERR_INVALID, "j out of range");
+        if (!pl->ddense) return fail(MMOT_ERR_UNSUPPORTED, "the dense product takes l <= 6, (l + 1) N <= 6144 and N^(l-1) < 2^31");
+        HIPCHK(launch_dense_product(pl->p.l, (int)pl->p.N, j, pl->hI.hoe, pl->hI.ieps, pl->dx, log_phi, log_J,
+                                    nullptr, nullptr, pl->ddense, pl->s));
+        return MMOT_OK;
+    } catch (...) {
+        return guard_fail();
+    }
+}
+
+int mmot_dense_sinkhorn_iter(const mmot_plan_t *pl, const double *log_u, double *log_phi, int64_t n_sweeps)
+{
+    try {
+        if (!pl || !log_u || !log_phi) return fail(MMOT_ERR_INVALID, "NULL argument");
+        if (n_sweeps < 0) return fail(MMOT_ERR_INVALID, "n_sweeps must be >= 0");
+        if (!pl->ddense) return fail(MMOT_ERR_UNSUPPORTED, "the dense product takes l <= 6, (l + 1) N <= 6144 and N^(l-1) < 2^31");
+        const long N = (long)pl->p.N;
+        for (int64_t it = 0; it < n_sweeps; ++it)
+            for (int j = 0; j < pl->p.l; ++j)
+                HIPCHK(launch_dense_product(pl->p.l, (int)N, j, pl->hI.hoe, pl->hI.ieps, pl->dx, log_phi, nullptr,
+                                            log_phi + (long)j * N, log_u + (long)j * N, pl->ddense, pl->s));
         return MMOT_OK;
     } catch (...) {
         return guard_fail();

@@ -50,6 +50,7 @@ def _units():
     units.append((os.path.join(HERE, "noalloc.cpp"), "noalloc.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "twod.cpp"), "twod.o", ["-x", "hip"]))
     units.append((os.path.join(HERE, "k_2d.hip"), "k_2d.o", []))
+    units.append((os.path.join(HERE, "k_dense.hip"), "k_dense.o", []))
     units.append((os.path.join(HERE, "tables.cpp"), "tables.o", []))
     return units
 

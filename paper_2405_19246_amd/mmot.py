@@ -84,7 +84,7 @@ EXPORTS = ["mmot_plan", "mmot_plan_footprint", "mmot_plan_destroy", "mmot_margin
            "mmot_serve_submit", "mmot_serve_poll", "mmot_serve_stop", "mmot_serve_cancel", "mmot_serve", "mmot_last_batch_kernel_ms",
            "mmot_last_batch_timing", "mmot_marginal_product_noalloc", "mmot_plan_2d", "mmot_plan_2d_destroy",
            "mmot_marginal_product_2d", "mmot_solve_2d", "mmot_objective_2d", "mmot_marginal_errors_2d",
-           "mmot_last_error"]
+           "mmot_dense_marginal_product", "mmot_dense_sinkhorn_iter", "mmot_last_error"]
 
 
 class MmotError(RuntimeError):
@@ -116,6 +116,8 @@ def lib() -> ctypes.CDLL:
         L.mmot_plan_destroy.argtypes = [_c_p]
         L.mmot_marginal_product.argtypes = [_c_p, _c_i32, _c_p, _c_p]
         L.mmot_sinkhorn_iter.argtypes = [_c_p, _c_p, _c_p, _c_i64, PP(_c_d)]
+        L.mmot_dense_marginal_product.argtypes = [_c_p, _c_i32, _c_p, _c_p]
+        L.mmot_dense_sinkhorn_iter.argtypes = [_c_p, _c_p, _c_p, _c_i64]
         L.mmot_solve.argtypes = [_c_p, _c_p, _c_p, PP(Result)]
         L.mmot_objective.argtypes = [_c_p, _c_p, PP(_c_d)]
         L.mmot_marginal_errors.argtypes = [_c_p, _c_p, _c_p, PP(_c_d)]
@@ -226,6 +228,22 @@ class Plan:
         po = _dev_f64(out, (self.N,), "out")
         _check(lib().mmot_marginal_product(self._h, int(j), _c_p(pa), _c_p(po)))
         return out
+
+    def dense_marginal_product(self, j: int, log_phi, out=None):
+        """mmot_dense_marginal_product: the O(N^l) definition on the device (comparison only)."""
+        import torch
+        pa = _dev_f64(log_phi, (self.l, self.N), "log_phi")
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device=log_phi.device)
+        po = _dev_f64(out, (self.N,), "out")
+        _check(lib().mmot_dense_marginal_product(self._h, int(j), _c_p(pa), _c_p(po)))
+        return out
+
+    def dense_sinkhorn_iter(self, log_u, log_phi, n_sweeps: int):
+        """mmot_dense_sinkhorn_iter: Gauss-Seidel sweeps with the dense products (in place)."""
+        pu = _dev_f64(log_u, (self.l, self.N), "log_u")
+        pa = _dev_f64(log_phi, (self.l, self.N), "log_phi")
+        _check(lib().mmot_dense_sinkhorn_iter(self._h, _c_p(pu), _c_p(pa), int(n_sweeps)))
 
     def sinkhorn_iter(self, log_u, log_phi, n_sweeps: int, want_err: bool = True):
         pu = _dev_f64(log_u, (self.l, self.N), "log_u")
