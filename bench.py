@@ -307,7 +307,8 @@ def next_rows(dev):
 
 def dense_comparator(dev, sweeps: int = 10):
     """The dense O(N^l) Sinkhorn on the device against the O(N) scans, both FP64, one instance of
-    l = 4, N = 100, eps = 1e-2 (the headline shape at N = 100), the same sweeps from the same start."""
+    l = 4, N = 100, eps = 1e-2 (the headline shape at N = 100), the same sweeps from the same start;
+    then one dense sweep at N = 1000 against the scans' time per sweep there."""
     import torch
     from paper_2405_19246_amd import inputs, mmot
     l, N, eps = 4, 100, 0.01
@@ -323,9 +324,23 @@ def dense_comparator(dev, sweeps: int = 10):
     _, td = timed(lambda: plan.dense_sinkhorn_iter(lu, ad, sweeps))
     _, tf = timed(lambda: plan.sinkhorn_iter(lu, af, sweeps, want_err=False))
     diff = float(torch.max(torch.abs((ad - ad.mean()) - (af - af.mean()))).item())
-    return dict(l=l, N=N, eps=eps, sweeps=sweeps, dense_ms_per_sweep=td / sweeps * 1e3,
-                scans_ms_per_sweep=tf / sweeps * 1e3, scans_speedup=td / tf,
-                dense_units_per_s=l * N * sweeps / td, max_potential_difference=diff)
+    out = dict(l=l, N=N, eps=eps, sweeps=sweeps, dense_ms_per_sweep=td / sweeps * 1e3,
+               scans_ms_per_sweep=tf / sweeps * 1e3, scans_speedup=td / tf,
+               dense_units_per_s=l * N * sweeps / td, max_potential_difference=diff)
+    # the headline shape itself (N = 1000): one dense sweep (10^12 terms per product)
+    N2 = 1000
+    u2 = inputs.marginals(l, N2, K=3, master_seed=0, instance=0)
+    lu2 = torch.tensor(np.log(u2), dtype=torch.float64, device=dev)
+    plan2 = mmot.Plan(l, N2, inputs.grid_step(N2), eps, precision=mmot.FP64, tol=-1.0, itr_max=sweeps,
+                      check_every=0)
+    b0 = torch.full((l, N2), -float(np.log(N2)), dtype=torch.float64, device=dev)
+    bd, bf = b0.clone(), b0.clone()
+    plan2.sinkhorn_iter(lu2, b0.clone(), 1, want_err=False)
+    _, td2 = timed(lambda: plan2.dense_sinkhorn_iter(lu2, bd, 1))
+    _, tf2 = timed(lambda: plan2.sinkhorn_iter(lu2, bf, sweeps, want_err=False))
+    out["n1000"] = dict(dense_ms_per_sweep=td2 * 1e3, dense_sweeps=1, scans_ms_per_sweep=tf2 / sweeps * 1e3,
+                        scans_speedup=td2 / (tf2 / sweeps))
+    return out
 
 
 def c4_batch(dev, count: int, itr_max: int):
