@@ -738,6 +738,11 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
         g_timer.on = true;
         HIPCHK(hipEventRecord(g_ev0, s));
     }
+    // the tiled groups need only the uploads above: their launches (on a stream
+    // of their own) overlap the persistent launches enqueued below
+    thread_local hipEvent_t ev_ready = nullptr;
+    if (!ev_ready) HIPCHK(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev_ready, s));
     LaunchTimer &tm = g_timer;
     const bool tmon = timed;
     auto tbegin = [&](int kind) { return tmon ? tm.begin(kind, s, &slot) : hipSuccess; };
@@ -765,7 +770,8 @@ int batch_launch(const Inst *hI, const Ptrs *hP, int count, int precision, const
             if (tiled[l][p].empty()) continue;
             if (tiled_res.empty()) tiled_res.resize(count);
             HIPCHK(tbegin(2));
-            const int rc = tiled_group_solve(l, tiled[l][p], count, hI, hP, p, o, flags, s, bb, tiled_res.data());
+            const int rc =
+                tiled_group_solve(l, tiled[l][p], count, hI, hP, p, o, flags, s, bb, tiled_res.data(), ev_ready);
             if (rc) return rc;
             HIPCHK(tend());
         }

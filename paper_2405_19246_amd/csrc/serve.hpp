@@ -38,9 +38,12 @@ hipError_t tile_buffers_reserve(BatchBuffers *bb, size_t jobs_bytes);
 
 // Tiled solves of the instances g (all with l marginals) of a batch of count:
 // sweeps in blocks of launches until each stops, then the FP64 objective; fills
-// hR[i] for i in g.  dI/dP of bb hold the batch's descriptors already.
+// hR[i] for i in g.  dI/dP of bb hold the batch's descriptors already.  The
+// tiled launches start after `start` (an event recorded on s) if given, else
+// after everything enqueued on s so far; later work on s waits for them.
 int tiled_group_solve(int l, const std::vector<int> &g, int count, const Inst *hI, const Ptrs *hP, int precision,
-                      const RunOpts &o, int flags, hipStream_t s, BatchBuffers *bb, Result *hR);
+                      const RunOpts &o, int flags, hipStream_t s, BatchBuffers *bb, Result *hR,
+                      hipEvent_t start = nullptr);
 
 // Allocates / frees a BatchBuffers set (hipMalloc; returns the HIP error).
 hipError_t batch_buffers_alloc(BatchBuffers *bb, size_t capacity);

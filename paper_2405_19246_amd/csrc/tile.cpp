@@ -155,7 +155,7 @@ static int tiled_group_solve_on(int l, const std::vector<int> &g, int count, con
 // default priority), ordered after the caller's stream by an event and before
 // its later work by another.
 int tiled_group_solve(int l, const std::vector<int> &g, int count, const Inst *hI, const Ptrs *hP, int precision,
-                      const RunOpts &o, int flags, hipStream_t s, BatchBuffers *bb, Result *hR)
+                      const RunOpts &o, int flags, hipStream_t s, BatchBuffers *bb, Result *hR, hipEvent_t start)
 {
     if (g.empty()) return MMOT_OK;
     thread_local hipStream_t side = nullptr;
@@ -165,8 +165,11 @@ int tiled_group_solve(int l, const std::vector<int> &g, int count, const Inst *h
         TCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
         TCHK(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
     }
-    TCHK(hipEventRecord(ev_in, s));
-    TCHK(hipStreamWaitEvent(side, ev_in, 0));
+    if (!start) {
+        TCHK(hipEventRecord(ev_in, s));
+        start = ev_in;
+    }
+    TCHK(hipStreamWaitEvent(side, start, 0));
     const int rc = tiled_group_solve_on(l, g, count, hI, hP, precision, o, flags, side, bb, hR);
     TCHK(hipEventRecord(ev_out, side));
     TCHK(hipStreamWaitEvent(s, ev_out, 0));
