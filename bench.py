@@ -601,6 +601,9 @@ def main():
                             p99_latency_s=st["p99_latency"], units_per_second=st["units_per_second"],
                             wall_seconds=st["wall_seconds"], workload=WORKLOAD + " requests")
         out["serve_mixed"] = serve_mixed(0.5, 8.0)
+        # a bounded sample of the mixed-batch distribution: its first 256 instances, at most 200
+        # sweeps each (most need more; the full configuration runs with --c4 COUNT)
+        out["c4_sample_256_cap200"] = c4_batch(dev, 256, 200)
         if args.c4 > 0:
             out["c4"] = c4_batch(dev, args.c4, args.c4_itr_max)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
