@@ -83,6 +83,8 @@ def test_null_plan_calls_are_invalid():
     L = mmot.lib()
     assert L.mmot_marginal_product(None, 0, None, None) == -1
     assert L.mmot_solve(None, None, None, None) == -1
+    assert L.mmot_dense_marginal_product(None, 0, None, None) == -1
+    assert L.mmot_dense_sinkhorn_iter(None, None, None, 1) == -1
     assert L.mmot_plan_destroy(None) == 0
     assert L.mmot_serve_stop(None) == 0
 
